@@ -1,0 +1,101 @@
+"""Synthetic-input generators: connectivity, orientation, seeds, watertight
+curving (no GPU)."""
+import numpy as np
+import pytest
+
+import meshgen
+from meshgen import BC_FARFIELD, BC_WALL
+from oracle.refelem import ref
+
+
+def reciprocal(m):
+    k = np.arange(m.K)[:, None]
+    f = np.arange(3)[None, :]
+    return (m.EToE[m.EToE, m.EToF] == k).all() and (m.EToF[m.EToE, m.EToF] == f).all()
+
+
+@pytest.mark.parametrize("mk", [
+    lambda: meshgen.periodic_square(6),
+    lambda: meshgen.periodic_square(5, perm_seed=None, curved_amplitude=0.05),
+    lambda: meshgen.cylinder_annulus(24, 6),
+    lambda: meshgen.naca4_ogrid(40, 8),
+])
+def test_connectivity_and_orientation(mk):
+    m = mk()
+    assert reciprocal(m)
+    assert (m.signed_area() > 0).all()
+    bnd = m.bc != 0
+    k, f = np.nonzero(bnd)
+    assert (m.EToE[k, f] == k).all() and (m.EToF[k, f] == f).all()
+    k, f = np.nonzero(~bnd)
+    assert (m.EToE[k, f] != k).all()
+
+
+def test_sizes_and_boundaries():
+    assert meshgen.periodic_square(16).K == 512
+    c = meshgen.cylinder_annulus()
+    assert c.K == 20000
+    assert (c.bc == BC_WALL).sum() == 200 and (c.bc == BC_FARFIELD).sum() == 200
+    a = meshgen.naca4_ogrid()
+    assert a.K == 120000 and (a.bc == BC_WALL).sum() == 600
+
+
+def test_seeds_are_reproducible():
+    a = meshgen.periodic_square(8)
+    b = meshgen.periodic_square(8)
+    np.testing.assert_array_equal(a.EToV, b.EToV)
+    np.testing.assert_array_equal(a.VX, b.VX)
+    c = meshgen.periodic_square(8, jitter_seed=1)
+    assert not np.array_equal(a.VX, c.VX)
+
+
+def test_permutation_keeps_geometry():
+    a = meshgen.periodic_square(6, perm_seed=None)
+    b = meshgen.periodic_square(6, perm_seed=4772)
+    perm = np.random.default_rng(4772).permutation(a.K)
+    np.testing.assert_array_equal(b.EToV, a.EToV[perm])
+    assert reciprocal(b)
+
+
+@pytest.mark.parametrize("P", [1, 3, 5])
+@pytest.mark.parametrize("mk", [
+    lambda: meshgen.cylinder_annulus(24, 6),
+    lambda: meshgen.naca4_ogrid(40, 8),
+    lambda: meshgen.periodic_square(5, perm_seed=7, curved_amplitude=0.05),
+])
+def test_curved_meshes_are_watertight(P, mk):
+    """Shared face nodes of neighbours coincide (modulo the period)."""
+    m = mk()
+    R = ref(P)
+    x, y = meshgen.node_coordinates(m, R.r, R.s)
+    Nfp = P + 1
+    Lp = m.info.get("periodic")
+    for f in range(3):
+        ks = np.nonzero(m.bc[:, f] == 0)[0]
+        kn = m.EToE[ks, f]
+        fn = m.EToF[ks, f]
+        for j in range(Nfp):
+            vm = R.Fmask[f, j]
+            vp = R.Fmask[fn, Nfp - 1 - j]
+            dx = x[ks, vm] - x[kn, vp]
+            dy = y[ks, vm] - y[kn, vp]
+            if Lp:
+                dx = dx - Lp[0] * np.round(dx / Lp[0])
+                dy = dy - Lp[1] * np.round(dy / Lp[1])
+            assert np.abs(dx).max() < 1e-12 and np.abs(dy).max() < 1e-12
+
+
+def test_vortex_state_is_radially_balanced():
+    """The isentropic vortex satisfies dp/dr = rho u_theta^2 / r."""
+    r = np.linspace(0.1, 3.0, 50)
+    x = 5.0 + r
+    y = 5.0 + 0 * r
+    h = 1e-6
+    def prim(xx):
+        U = meshgen.isentropic_vortex(xx, y)
+        rho = U[0]
+        p = 0.4 * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / rho)
+        return rho, U[2] / rho, p
+    rho, vt, _ = prim(x)
+    dp = (prim(x + h)[2] - prim(x - h)[2]) / (2 * h)
+    np.testing.assert_allclose(dp, rho * vt ** 2 / r, rtol=1e-6, atol=1e-9)
