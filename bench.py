@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X nodal DG Euler solver.
+
+One "step" is one full LSERK(5,4) step of the hot path: the FP64 CFL
+reduction and five fused stage kernels (volume term, face gather with
+Lax-Friedrichs flux and boundary states, LIFT, Runge-Kutta update) over the
+whole mesh.  The default workload is the subsonic cylinder: M=0.38 flow past
+a unit circle, 20,000 triangles with cubic curved wall elements, P=4,
+slip wall + characteristic far field, CFL 0.5, 2000 steps, FP32.
+
+Prints one JSON line: value = RK-stage DOF-updates/s (4 Np K x 5 stages x
+steps / wall time, inputs resident in HBM), the FP64-plain path's rate on the
+same workload, the dominant kernel's HBM roofline (algorithmic bytes over its
+average launch time measured with HIP events inside the timed region) and the
+FP64 CPU oracle timed on this host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RK-stage DOF-updates/s (FP32/batched vs FP64 plain) + p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "cylinder": "Subsonic flow past a unit circle, Mach 0.38, AoA 0: annulus r in [1,20], "
+                "20,000 triangles (200x50, graded, seeded jitter), cubic curved wall elements, "
+                "P=4 (Np=15), slip wall + characteristic far field, CFL 0.5",
+    "roofline": "Isentropic vortex on a seeded, jittered periodic square, 999,698 straight "
+                "triangles (2x707x707), P=5 (Np=21, 84M DOF), CFL 0.5",
+    "vortex": "Isentropic vortex on the periodic square [0,10]^2, 512 jittered, permuted "
+              "triangles, P=2 (Np=6), CFL 0.5",
+    "airfoil": "Transonic flow, Mach 0.8, AoA 1.25 deg, 4-digit 12% airfoil, far field R=30, "
+               "120,000 triangles, cubic curved wall, P=3 (Np=10), Persson-Peraire sensor + "
+               "LDG artificial viscosity, CFL 0.5",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1208_4772_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_stage_bytes(case, s):
+    """HBM bytes one fused stage launch must move (averaged over the 5 stages):
+    state in + out and the Runge-Kutta register R (read in 4 of 5 stages,
+    written in all), the neighbours' face traces once per interior face side,
+    geometric factors (13 values for a straight element, 4 Np + 9 Nfp for a
+    curved one) and 12 bytes of connectivity per element."""
+    import numpy as np
+    K, Np, Nfp = case.K, case.Np, case.P + 1
+    m = case.mesh
+    interior_sides = int((m.bc == 0).sum())
+    if m.node_displacement is not None:
+        curved = K
+    elif m.curve is not None:
+        curved = int((m.bc == 1).any(axis=1).sum())
+    else:
+        curved = 0
+    state = K * 4 * Np * s * (3 + 4 / 5)
+    traces = interior_sides * Nfp * 4 * s
+    geom = (K - curved) * 13 * s + curved * (4 * Np + 9 * Nfp) * s
+    conn = 12 * K
+    return state + traces + geom + conn, dict(curved=curved, interior_sides=interior_sides)
+
+
+def load_traffic(workload, precision, launch_bytes):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_stage_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(case, budget_s=15.0):
+    """The FP64 oracle on this host's cores: one warm rhs to size the sample,
+    then as many full steps of the same mesh as fit the budget."""
+    from oracle import oracle as orc
+    from oracle.refelem import ref
+    import numpy as np
+    R = ref(case.P)
+    import meshgen
+    oc = meshgen.make_case(case.name, R.r, R.s)
+    o = orc.Oracle.for_case(oc)
+    t0 = time.perf_counter()
+    o.rhs(oc.U0)
+    t1 = time.perf_counter() - t0
+    steps = max(1, int(budget_s / (5.5 * t1)))
+    t0 = time.perf_counter()
+    _, info = o.run(oc.U0, steps)
+    el = time.perf_counter() - t0
+    dofs = oc.dofs()
+    return dict(value=dofs * 5 * steps / el, unit="DOF-updates/s", cores=orc.max_threads(),
+                kind="oracle",
+                sample=f"{steps} full LSERK steps of the same {oc.K}-element P={oc.P} mesh "
+                       f"(of {case.steps}), FP64, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed LSERK steps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cylinder", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="only run a device-to-device copy of this many GiB (HBM peak probe and "
+                         "the known-size kernel that scales the traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
+              f"multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1208_4772_amd import dg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "avg_ms": ms, "achieved_GBs": 2 * 4 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
+    P = {"cylinder": 4, "roofline": 5, "vortex": 2, "airfoil": 3}[args.workload]
+    r, s = dg.reference_nodes(P)
+    case = meshgen.make_case(args.workload, r, s)
+    steps = case.steps if args.steps is None else args.steps
+    log(f"workload {args.workload}: K={case.K} P={case.P} Np={case.Np} DOF={case.dofs()} "
+        f"steps={steps} warmup={args.warmup}")
+
+    def timed_run(precision, nsteps, warmup, kernel_timing):
+        sol = dg.Solver.from_case(case, precision, device="cuda:0")
+        U0 = sol.state(case.U0)
+        U = U0.clone()
+        if warmup:
+            sol.run(U, warmup)
+        U.copy_(U0)
+        sol.set_kernel_timing(kernel_timing)
+        sol.kernel_time()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sol.run(U, nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, kn = sol.kernel_time()
+        ok = bool(torch.isfinite(U).all().item())
+        sol.close()
+        return wall, st, kms, kn, ok
+
+    wall, st, kms, kn, ok = timed_run(args.precision, steps, args.warmup, True)
+    if not ok or st.status != 0:
+        raise SystemExit("state became non-finite in the timed run")
+    dofs = case.dofs()
+    value = dofs * 5 * steps / wall
+    log(f"{args.precision}: {wall * 1e3:.2f} ms for {steps} steps -> {value:.4e} DOF-updates/s "
+        f"(device events {st.wall_s * 1e3:.2f} ms); stage kernel {kn} launches, "
+        f"avg {kms / max(kn, 1) * 1e3:.2f} us")
+
+    sbytes = 4 if args.precision == "fp32" else 8
+    launch_bytes, geo_info = algorithmic_stage_bytes(case, sbytes)
+    avg_s = kms / max(kn, 1) * 1e-3
+    achieved = launch_bytes / avg_s / 1e9
+    traffic = load_traffic(args.workload, args.precision, launch_bytes)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel=f"k_stage<{'float' if sbytes == 4 else 'double'},P={case.P}>",
+                    avg_launch_us=round(avg_s * 1e6, 3),
+                    algorithmic_bytes_per_launch=int(launch_bytes))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "K": case.K, "P": case.P,
+                   "dof": dofs, "precision": args.precision,
+                   "curved_elements": geo_info["curved"]},
+        "roofline": roofline,
+    }
+    if not args.no_fp64 and args.precision == "fp32":
+        w64, st64, k64, n64, ok64 = timed_run("fp64", steps, args.warmup, True)
+        out["fp64_plain"] = dict(value=dofs * 5 * steps / w64, ms_per_step=w64 * 1e3 / steps,
+                                 stage_kernel_avg_us=round(k64 / max(n64, 1) * 1e3, 3),
+                                 finite=ok64)
+        out["fp32_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 3)
+        log(f"fp64 plain: {w64 * 1e3:.2f} ms -> {out['fp64_plain']['value']:.4e} DOF-updates/s")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * dg.h -- C ABI of the MI355X nodal discontinuous Galerkin solver for the 2D
+ * Euler equations on unstructured, curved (isoparametric) triangles.
+ *
+ * What is computed (Siebenborn, Schulz, Schmidt, "A curved-element
+ * unstructured discontinuous Galerkin method on GPUs for the Euler
+ * equations"):
+ *   dU/dt + div F(U) = 0 (Section 2, eq. conservation_law) discretised per
+ *   element with a numerical flux on the element boundary (eq. weak_dg,
+ *   local Lax-Friedrichs), mapped to the reference triangle through the
+ *   metric terms of D Psi and J (Section 2), in the nodal strong form
+ *       dU/dt = -(r_x Dr F + s_x Ds F + r_y Dr G + s_y Ds G)
+ *               + LIFT [Fscale (n.F(U-) - F*)]
+ *   (the semi-discrete system, eq. semidiscrete, with collocation at the
+ *   nodes instead of cubature), optional Persson-Peraire artificial
+ *   viscosity (Section 2: S_k, the eps_k ramp, q = sqrt(eps) grad U), and
+ *   the low-storage 5-stage 4th-order Runge-Kutta scheme of Carpenter and
+ *   Kennedy (Section 2).  The gas is perfect (Section 5) with 4 conserved
+ *   fields (rho, rho u, rho v, E).
+ *
+ * Conventions
+ *   - Reference triangle T = {r, s >= -1, r + s <= 0}, vertices
+ *     v1=(-1,-1), v2=(1,-1), v3=(-1,1); faces 0: v1->v2, 1: v2->v3,
+ *     2: v3->v1.  Elements must be counter-clockwise (J > 0).
+ *   - Nodes per element Np = (P+1)(P+2)/2 in the order dg_reference_nodes
+ *     returns; Nfp = P+1 nodes per face.
+ *   - Neighbour face node of face node j is node Nfp-1-j of the
+ *     neighbour's face (shared edges run in opposite directions).
+ *   - State arrays are element-major [K][4][Np] in the handle's precision
+ *     (double for DG_FP64_PLAIN, float for DG_FP32), on the device.
+ *   - Boundary faces have EToE[k][f] = k, EToF[k][f] = f and a non-zero bc
+ *     code; periodic seams are ordinary interior connectivity.
+ *
+ * Ownership: the caller owns every state and work buffer and the stream
+ * (a hipStream_t passed as void*, NULL = the null stream); the handle owns
+ * its device geometry and operator tables and frees them in
+ * dg_mesh_destroy.  The library never frees caller memory.
+ *
+ * Errors: every function returns DG_OK (0) or a negative DG_E* code and
+ * sets a thread-local message (dg_last_error).  No exceptions cross the ABI.
+ * A handle is not thread-safe; different handles may run concurrently on
+ * different streams.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum dg_status {
+    DG_OK = 0,
+    DG_EINVAL = -1,      /* bad argument or inconsistent mesh */
+    DG_ENOMEM = -2,      /* device allocation failed */
+    DG_EGEOM = -3,       /* J <= 0 at some node, or mismatched face normals */
+    DG_ENONFINITE = -4,  /* state became non-finite or rho <= 0 or p <= 0 */
+    DG_EDEVICE = -5,     /* HIP runtime error */
+    DG_EBUSY = -6        /* resource exhausted (reserved) */
+};
+
+enum dg_precision {
+    DG_FP64_PLAIN = 0,   /* FP64 throughout; straightforward VALU kernels */
+    DG_FP32 = 2          /* FP32 state and fused stage kernel; FP64 setup,
+                            time step and reductions */
+};
+
+enum dg_bc { DG_BC_INTERIOR = 0, DG_BC_WALL = 1, DG_BC_FARFIELD = 2 };
+
+/* Message of the last error on this thread ("" if none). */
+const char *dg_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int dg_version(void);
+
+/* Reference nodes of order P (1 <= P <= 5): warp-and-blend nodes of
+ * Warburton (2006), the family the paper cites for its collocation points
+ * (Section 2), in rows of constant s (increasing s), increasing r within a
+ * row.  r and s are host arrays of Np doubles, written by the call. */
+int dg_reference_nodes(int P, double *r, double *s);
+
+/* Face node ids (host int array of 3*Nfp): face f's nodes in
+ * counter-clockwise traversal order. */
+int dg_face_nodes(int P, int *fmask);
+
+/* Reference operators of order P as built by the library (host, FP64,
+ * row-major): Dr, Ds [Np*Np] (differentiation D_r = V_r V^{-1}, Section 2),
+ * LIFT [Np*3*Nfp] (M^{-1} times the face mass matrix, the reference form of
+ * M_k^{-1} M_dOmega in eq. semidiscrete), Vinv [Np*Np] (nodal to
+ * orthonormal modal coefficients, f = V f_hat).  Any pointer may be NULL. */
+int dg_reference_operators(int P, double *Dr, double *Ds, double *LIFT, double *Vinv);
+
+typedef struct {
+    int K;                        /* elements, >= 1 */
+    int P;                        /* order, 1..5 */
+    int precision;                /* enum dg_precision */
+    double gamma;                 /* ratio of specific heats, > 1 */
+    double cfl;                   /* CFL number of the automatic step, > 0 */
+    const int *EToE;              /* host [K][3] neighbour element */
+    const int *EToF;              /* host [K][3] neighbour face */
+    const signed char *bc;        /* host [K][3] enum dg_bc */
+    const double *x, *y;          /* host [K][Np] node coordinates (curved) */
+    double freestream[4];         /* far-field state (rho, rho u, rho v, E) */
+    int av_enable;                /* Persson-Peraire artificial viscosity */
+    double av_eps0;               /* eps_max = av_eps0 * h_k / P */
+    double av_s0;                 /* ramp centre; NaN: -4 log10 P */
+    double av_kappa;              /* ramp half-width, > 0 */
+} dg_mesh_desc;
+
+typedef struct dg_mesh dg_mesh;   /* opaque handle */
+
+typedef struct {
+    int steps;                    /* steps taken by the call */
+    int status;                   /* DG_OK or DG_ENONFINITE */
+    double t;                     /* simulated time advanced by the call */
+    double dt_min, dt_max;        /* time steps used */
+    double totals[4];             /* conserved totals at the end (FP64) */
+    double residual[4];           /* ||dU/dt||_inf per field at the end */
+    double wall_s;                /* device time of the call (HIP events) */
+    double dof_updates_per_s;     /* 4*Np*K*5*steps / wall_s */
+} dg_run_stats;
+
+/* Validate the mesh, build operators, upload connectivity and compute the
+ * geometric factors in FP64 on the device (metric terms of the
+ * isoparametric map per node, Section 2; face normals, sJ, Fscale per face
+ * node).  Checks: 1 <= P <= 5, K >= 1, reciprocal connectivity
+ * (EToE[EToE[k][f]][EToF[k][f]] = k), valid bc codes, J > 0 at every node
+ * (else DG_EGEOM), n- = -n+ within 1e-8 at interior face nodes (else
+ * DG_EGEOM).  Synchronises the stream.  *out is NULL on error. */
+int dg_mesh_setup(const dg_mesh_desc *desc, void *stream, dg_mesh **out);
+
+int dg_mesh_destroy(dg_mesh *mesh);
+
+/* Bytes of one state array [K][4][Np] and of the work buffer that
+ * dg_step/dg_run need. */
+int dg_buffer_bytes(const dg_mesh *mesh, size_t *state_bytes, size_t *work_bytes);
+
+/* rhs = dU/dt for state U (device pointers, [K][4][Np]).  t is accepted for
+ * interface completeness; the boundary data are time-independent.
+ * Enqueues only. */
+int dg_rhs(dg_mesh *mesh, const void *U, void *rhs, double t, void *stream);
+
+/* One LSERK(5,4) step of U in place.  dt > 0: that step; dt <= 0: the CFL
+ * step computed on the device from U (dt = cfl / max over face nodes of
+ * (P+1)^2/2 Fscale (|v|+c) + (P+1)^4/4 Fscale^2 eps).  work: device buffer
+ * of dg_buffer_bytes' work_bytes.  Enqueues only (no host round trip). */
+int dg_step(dg_mesh *mesh, void *U, void *work, double dt, void *stream);
+
+/* nsteps CFL steps of U in place, then totals and residual; synchronises
+ * and fills *stats (may be NULL).  Returns DG_ENONFINITE if the state
+ * became non-finite, rho <= 0 or p <= 0 at any step. */
+int dg_run(dg_mesh *mesh, void *U, void *work, int nsteps, dg_run_stats *stats, void *stream);
+
+/* Conserved totals sum_k sum_i w_ki U_ki, w_ki = sum_j M_ij J_kj, in FP64
+ * (host out[4]).  Synchronises. */
+int dg_totals(dg_mesh *mesh, const void *U, double out[4], void *stream);
+
+/* Residual ||rhs(U)||_inf per field (host out[4]), the convergence monitor
+ * of the paper (Section 5).  work as for dg_step.  Synchronises. */
+int dg_residual(dg_mesh *mesh, const void *U, void *work, double out[4], void *stream);
+
+/* Element viscosities eps_k of state U (device out [K] doubles).  Enqueues
+ * only.  Returns DG_EINVAL if the mesh was set up without viscosity. */
+int dg_viscosity(dg_mesh *mesh, const void *U, double *eps, void *stream);
+
+/* Per-launch timing of the fused stage kernel.  With timing enabled,
+ * dg_step and dg_run bracket every stage-kernel launch with a pair of HIP
+ * events on the caller's stream (no synchronisation).  dg_kernel_time
+ * synchronises the stream, adds up the elapsed times of all bracketed
+ * launches since the last call, returns the total in milliseconds and the
+ * number of launches, and resets both.  Used by benchmarks to report the
+ * dominant kernel's average duration measured inside the timed region. */
+int dg_set_kernel_timing(dg_mesh *mesh, int enable);
+int dg_kernel_time(dg_mesh *mesh, void *stream, double *stage_ms_total, long *stage_launches);
+
+/* Device flag of the last dg_step/dg_run: 1 if a non-finite state,
+ * rho <= 0 or p <= 0 was seen.  Synchronises the stream. */
+int dg_status(dg_mesh *mesh, void *stream, int *device_flag);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

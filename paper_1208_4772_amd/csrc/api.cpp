@@ -1,0 +1,527 @@
+// C ABI of the solver: argument validation, device tables, and the
+// per-step launch sequence (CFL reduction, then five stages, each optionally
+// preceded by the sensor and the viscous-gradient kernels).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "common.hpp"
+#include "launch.hpp"
+#include "refelem.hpp"
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(DG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+struct dg_mesh {
+    DevMesh dm;
+    int precision = DG_FP64_PLAIN;
+    size_t elem_bytes = 8;
+    std::vector<void *> allocs;
+    double *eps64_scratch = nullptr;
+
+    template <typename T>
+    int alloc(T **p, size_t count) {
+        void *q = nullptr;
+        if (count == 0) count = 1;
+        if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        allocs.push_back(q);
+        *p = static_cast<T *>(q);
+        return DG_OK;
+    }
+    ~dg_mesh() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+    // per-launch stage-kernel timing (event pairs, reused across calls)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+    double stage_ms = 0.0;
+    long stage_launches = 0;
+
+    hipError_t time_begin(hipStream_t st) {
+        if (!timing) return hipSuccess;
+        if (events_used + 2 > events.size()) {
+            for (int n = 0; n < 64; ++n) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                events.push_back(e);
+            }
+        }
+        return hipEventRecord(events[events_used], st);
+    }
+    hipError_t time_end(hipStream_t st) {
+        if (!timing) return hipSuccess;
+        hipError_t r = hipEventRecord(events[events_used + 1], st);
+        events_used += 2;
+        return r;
+    }
+    // after the stream has synchronised
+    hipError_t time_collect() {
+        for (size_t n = 0; n + 1 < events_used; n += 2) {
+            float ms = 0.f;
+            hipError_t r = hipEventElapsedTime(&ms, events[n], events[n + 1]);
+            if (r != hipSuccess) return r;
+            stage_ms += ms;
+            stage_launches += 1;
+        }
+        events_used = 0;
+        return hipSuccess;
+    }
+
+    size_t state_count() const { return size_t(dm.K) * kFields * dm.Np; }
+    size_t state_bytes() const { return state_count() * elem_bytes; }
+    // work layout: R | A | B | Q (2x state, AV) | eps [K] (AV)
+    size_t off_R() const { return 0; }
+    size_t off_A() const { return align256(state_bytes()); }
+    size_t off_B() const { return 2 * align256(state_bytes()); }
+    size_t off_Q() const { return 3 * align256(state_bytes()); }
+    size_t off_eps() const { return off_Q() + (dm.av ? align256(2 * state_bytes()) : 0); }
+    size_t work_bytes() const { return off_eps() + (dm.av ? align256(size_t(dm.K) * elem_bytes) : 0); }
+};
+
+extern "C" {
+
+const char *dg_last_error(void) { return g_err.c_str(); }
+
+int dg_version(void) { return 100; }
+
+int dg_reference_nodes(int P, double *r, double *s) {
+    RefOps o;
+    if (!build_reference(P, o)) return fail(DG_EINVAL, "order P must be 1..5");
+    if (!r || !s) return fail(DG_EINVAL, "null output");
+    std::memcpy(r, o.r.data(), sizeof(double) * o.Np);
+    std::memcpy(s, o.s.data(), sizeof(double) * o.Np);
+    return DG_OK;
+}
+
+int dg_face_nodes(int P, int *fmask) {
+    RefOps o;
+    if (!build_reference(P, o)) return fail(DG_EINVAL, "order P must be 1..5");
+    if (!fmask) return fail(DG_EINVAL, "null output");
+    std::memcpy(fmask, o.fmask.data(), sizeof(int) * 3 * o.Nfp);
+    return DG_OK;
+}
+
+int dg_reference_operators(int P, double *Dr, double *Ds, double *LIFT, double *Vinv) {
+    RefOps o;
+    if (!build_reference(P, o)) return fail(DG_EINVAL, "order P must be 1..5");
+    if (Dr) std::memcpy(Dr, o.Dr.data(), sizeof(double) * o.Dr.size());
+    if (Ds) std::memcpy(Ds, o.Ds.data(), sizeof(double) * o.Ds.size());
+    if (LIFT) std::memcpy(LIFT, o.LIFT.data(), sizeof(double) * o.LIFT.size());
+    if (Vinv) std::memcpy(Vinv, o.Vinv.data(), sizeof(double) * o.Vinv.size());
+    return DG_OK;
+}
+
+int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(DG_EINVAL, "desc is NULL");
+    if (d->P < 1 || d->P > 5) return fail(DG_EINVAL, "order P must be 1..5");
+    if (d->K < 1) return fail(DG_EINVAL, "K must be >= 1");
+    if (d->precision != DG_FP64_PLAIN && d->precision != DG_FP32)
+        return fail(DG_EINVAL, "precision must be DG_FP64_PLAIN or DG_FP32");
+    if (!(d->gamma > 1.0)) return fail(DG_EINVAL, "gamma must be > 1");
+    if (!(d->cfl > 0.0)) return fail(DG_EINVAL, "cfl must be > 0");
+    if (!d->EToE || !d->EToF || !d->bc || !d->x || !d->y) return fail(DG_EINVAL, "null mesh array");
+    if (d->av_enable && (!(d->av_kappa > 0.0) || !(d->av_eps0 >= 0.0)))
+        return fail(DG_EINVAL, "av_kappa must be > 0 and av_eps0 >= 0");
+    const int K = d->K, P = d->P;
+    RefOps ref;
+    if (!build_reference(P, ref)) return fail(DG_EINVAL, "reference element construction failed");
+    const int Np = ref.Np, Nfp = ref.Nfp;
+    // the kernels' compile-time face table must agree with the nodes
+    for (int f = 0; f < 3; ++f)
+        for (int j = 0; j < Nfp; ++j)
+            if (ref.fmask[f * Nfp + j] != face_node(P, f, j))
+                return fail(DG_EINVAL, "internal: face node table mismatch");
+    // connectivity checks (host)
+    std::vector<int> nbr(size_t(K) * 3), finfo(K, 0);
+    for (long k = 0; k < K; ++k) {
+        int info = 0;
+        for (int f = 0; f < 3; ++f) {
+            const int kn = d->EToE[k * 3 + f], fn = d->EToF[k * 3 + f];
+            const int code = d->bc[k * 3 + f];
+            if (code < 0 || code > 2)
+                return fail(DG_EINVAL, "bc code must be 0, 1 or 2 (element " + std::to_string(k) + ")");
+            if (kn < 0 || kn >= K || fn < 0 || fn > 2)
+                return fail(DG_EINVAL, "EToE/EToF out of range at element " + std::to_string(k));
+            if (code == 0) {
+                if (kn == k && fn == f)
+                    return fail(DG_EINVAL, "interior face glued to itself at element " + std::to_string(k));
+                if (d->EToE[kn * 3 + fn] != k || d->EToF[kn * 3 + fn] != f)
+                    return fail(DG_EINVAL, "non-reciprocal connectivity at element " + std::to_string(k));
+                if (d->bc[kn * 3 + fn] != 0)
+                    return fail(DG_EINVAL, "interior face matched to a boundary face at element " +
+                                               std::to_string(k));
+            } else if (kn != k || fn != f) {
+                return fail(DG_EINVAL, "boundary face must have EToE=k, EToF=f (element " +
+                                           std::to_string(k) + ")");
+            }
+            nbr[k * 3 + f] = kn;
+            info |= (fn & 3) << (4 * f);
+            info |= (code & 3) << (4 * f + 2);
+        }
+        finfo[k] = info;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    dg_mesh *m = new dg_mesh();
+    DevMesh &dm = m->dm;
+    dm.K = K;
+    dm.P = P;
+    dm.Np = Np;
+    dm.Nfp = Nfp;
+    dm.fp32 = d->precision == DG_FP32;
+    dm.av = d->av_enable != 0;
+    dm.gamma = d->gamma;
+    dm.cfl = d->cfl;
+    for (int c = 0; c < 4; ++c) dm.qinf[c] = d->freestream[c];
+    dm.av_s0 = std::isnan(d->av_s0) ? -4.0 * std::log10(double(P)) : d->av_s0;
+    dm.av_kappa = d->av_kappa;
+    m->precision = d->precision;
+    m->elem_bytes = dm.fp32 ? 4 : 8;
+
+    auto cleanup = [&](int code) {
+        delete m;
+        return code;
+    };
+    int *nbr_d, *finfo_d, *flag_d, *count_d;
+    double *x_d, *y_d, *geo64, *fgeo64, *wmass, *emax64, *ops64, *scal, *partial;
+    const size_t nops = ops_size(Np, Nfp);
+    int rc = DG_OK;
+    if ((rc = m->alloc(&nbr_d, size_t(K) * 3)) || (rc = m->alloc(&finfo_d, size_t(K))) ||
+        (rc = m->alloc(&flag_d, 1)) || (rc = m->alloc(&count_d, 4)) ||
+        (rc = m->alloc(&x_d, size_t(K) * Np)) || (rc = m->alloc(&y_d, size_t(K) * Np)) ||
+        (rc = m->alloc(&geo64, size_t(K) * 4 * Np)) || (rc = m->alloc(&fgeo64, size_t(K) * 9 * Nfp)) ||
+        (rc = m->alloc(&wmass, size_t(K) * Np)) || (rc = m->alloc(&emax64, size_t(K))) ||
+        (rc = m->alloc(&ops64, nops + size_t(Np) * Np)) || (rc = m->alloc(&scal, S_NSCAL)) ||
+        (rc = m->alloc(&partial, size_t(partial_slots(K, P)) * 4 + 4)))
+        return cleanup(rc);
+    dm.nbr = nbr_d;
+    dm.finfo = finfo_d;
+    dm.flag = flag_d;
+    dm.count = count_d;
+    dm.geo64 = geo64;
+    dm.fgeo64 = fgeo64;
+    dm.wmass = wmass;
+    dm.emax64 = emax64;
+    dm.ops64 = ops64;
+    dm.scal = scal;
+    dm.partial = partial;
+    dm.npartial = partial_slots(K, P);
+
+    std::vector<double> ops(nops + size_t(Np) * Np);
+    std::memcpy(ops.data() + off_Dr(Np, Nfp), ref.Dr.data(), sizeof(double) * Np * Np);
+    std::memcpy(ops.data() + off_Ds(Np, Nfp), ref.Ds.data(), sizeof(double) * Np * Np);
+    std::memcpy(ops.data() + off_LIFT(Np, Nfp), ref.LIFT.data(), sizeof(double) * Np * 3 * Nfp);
+    std::memcpy(ops.data() + off_Vinv(Np, Nfp), ref.Vinv.data(), sizeof(double) * Np * Np);
+    std::memcpy(ops.data() + nops, ref.M.data(), sizeof(double) * Np * Np);
+
+#define SETUP_TRY(expr)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            fail(DG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+            return cleanup(DG_EDEVICE);                                                     \
+        }                                                                                   \
+    } while (0)
+
+    SETUP_TRY(hipMemcpyAsync(nbr_d, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(finfo_d, finfo.data(), sizeof(int) * finfo.size(), hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(x_d, d->x, sizeof(double) * size_t(K) * Np, hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(y_d, d->y, sizeof(double) * size_t(K) * Np, hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemcpyAsync(ops64, ops.data(), sizeof(double) * ops.size(), hipMemcpyHostToDevice, st));
+    SETUP_TRY(hipMemsetAsync(count_d, 0, sizeof(int) * 4, st));
+    SETUP_TRY(hipMemsetAsync(flag_d, 0, sizeof(int), st));
+    SETUP_TRY(launch_reset_scalars(dm, st));
+    SETUP_TRY(launch_geometry(dm, x_d, y_d, geo64, fgeo64, wmass, emax64, d->av_eps0, st));
+    SETUP_TRY(launch_check_normals(dm, st));
+    int counts[4] = {0, 0, 0, 0};
+    SETUP_TRY(hipMemcpyAsync(counts, count_d, sizeof(counts), hipMemcpyDeviceToHost, st));
+    SETUP_TRY(hipStreamSynchronize(st));
+    if (counts[0] > 0) {
+        fail(DG_EGEOM, std::to_string(counts[0]) + " nodes with J <= 0 (clockwise or folded elements)");
+        return cleanup(DG_EGEOM);
+    }
+    if (counts[1] > 0) {
+        fail(DG_EGEOM, std::to_string(counts[1]) +
+                           " interior face nodes whose normal is not minus the neighbour's");
+        return cleanup(DG_EGEOM);
+    }
+    if (dm.fp32) {
+        float *geo32, *fgeo32, *emax32, *ops32;
+        if ((rc = m->alloc(&geo32, size_t(K) * 4 * Np)) || (rc = m->alloc(&fgeo32, size_t(K) * 9 * Nfp)) ||
+            (rc = m->alloc(&emax32, size_t(K))) || (rc = m->alloc(&ops32, nops)))
+            return cleanup(rc);
+        SETUP_TRY(launch_cast(geo64, geo32, size_t(K) * 4 * Np, st));
+        SETUP_TRY(launch_cast(fgeo64, fgeo32, size_t(K) * 9 * Nfp, st));
+        SETUP_TRY(launch_cast(emax64, emax32, size_t(K), st));
+        SETUP_TRY(launch_cast(ops64, ops32, nops, st));
+        dm.geo32 = geo32;
+        dm.fgeo32 = fgeo32;
+        dm.emax32 = emax32;
+        dm.ops32 = ops32;
+        SETUP_TRY(hipStreamSynchronize(st));
+    }
+    *out = m;
+    g_err.clear();
+    return DG_OK;
+#undef SETUP_TRY
+}
+
+int dg_mesh_destroy(dg_mesh *m) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    (void)hipDeviceSynchronize();
+    delete m;
+    return DG_OK;
+}
+
+int dg_buffer_bytes(const dg_mesh *m, size_t *state_bytes, size_t *work_bytes) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (state_bytes) *state_bytes = m->state_bytes();
+    if (work_bytes) *work_bytes = m->work_bytes();
+    return DG_OK;
+}
+
+static int check_ptr(const void *p, const char *what) {
+    if (!p) return fail(DG_EINVAL, std::string(what) + " is NULL");
+    return DG_OK;
+}
+
+// sensor + viscous gradient of state U into the work buffer
+static int av_prepare(dg_mesh *m, const void *U, char *work, hipStream_t st) {
+    void *eps = work + m->off_eps();
+    void *Q = work + m->off_Q();
+    HIP_TRY(launch_sensor(m->dm, U, eps, st));
+    HIP_TRY(launch_avgrad(m->dm, U, eps, Q, st));
+    return DG_OK;
+}
+
+int dg_rhs(dg_mesh *m, const void *U, void *rhs, double t, void *stream) {
+    (void)t;
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(rhs, "rhs")) return rc;
+    if (U == rhs) return fail(DG_EINVAL, "U and rhs must not alias");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (m->dm.av) {
+        // viscosity scratch for a pure rhs evaluation
+        if (!m->eps64_scratch) {
+            void *q = nullptr;
+            size_t bytes = align256(size_t(m->dm.K) * m->elem_bytes) + 2 * m->state_bytes();
+            if (hipMalloc(&q, bytes) != hipSuccess) return fail(DG_ENOMEM, "rhs scratch allocation failed");
+            m->allocs.push_back(q);
+            m->eps64_scratch = static_cast<double *>(q);
+        }
+        char *base = reinterpret_cast<char *>(m->eps64_scratch);
+        void *eps = base;
+        void *Q = base + align256(size_t(m->dm.K) * m->elem_bytes);
+        HIP_TRY(launch_sensor(m->dm, U, eps, st));
+        HIP_TRY(launch_avgrad(m->dm, U, eps, Q, st));
+        HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, rhs, 0, eps, Q, st));
+        return DG_OK;
+    }
+    HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, rhs, 0, nullptr, nullptr, st));
+    return DG_OK;
+}
+
+// One step: dt reduction on the device, then five stages ping-ponging
+// U -> A -> B -> A -> B -> U so that no stage writes the buffer whose face
+// traces other workgroups are still reading.
+static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st) {
+    char *w = static_cast<char *>(work);
+    void *R = w + m->off_R();
+    void *A = w + m->off_A();
+    void *B = w + m->off_B();
+    void *Q = m->dm.av ? w + m->off_Q() : nullptr;
+    void *eps = m->dm.av ? w + m->off_eps() : nullptr;
+    void *in[5] = {U, A, B, A, B};
+    void *out[5] = {A, B, A, B, U};
+    if (m->dm.av) {
+        if (int rc = av_prepare(m, U, w, st)) return rc;
+    }
+    HIP_TRY(launch_cfl(m->dm, U, eps, dt, st));
+    for (int s = 0; s < 5; ++s) {
+        if (m->dm.av && s > 0) {
+            if (int rc = av_prepare(m, in[s], w, st)) return rc;
+        }
+        HIP_TRY(m->time_begin(st));
+        HIP_TRY(launch_stage(m->dm, in[s], out[s], R, nullptr, s, eps, Q, st));
+        HIP_TRY(m->time_end(st));
+    }
+    return DG_OK;
+}
+
+int dg_step(dg_mesh *m, void *U, void *work, double dt, void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(work, "work")) return rc;
+    return step_impl(m, U, work, dt, static_cast<hipStream_t>(stream));
+}
+
+int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(work, "work")) return rc;
+    if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(launch_reset_scalars(m->dm, st));
+    HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int n = 0; n < nsteps; ++n) {
+        if (int rc = step_impl(m, U, work, 0.0, st)) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    // diagnostics at the end: totals and the residual ||rhs(U)||_inf
+    char *w = static_cast<char *>(work);
+    void *scratch = w + m->off_A();
+    HIP_TRY(launch_totals(m->dm, U, st));
+    if (m->dm.av) {
+        if (int rc = av_prepare(m, U, w, st)) return rc;
+    }
+    HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, scratch, 0, m->dm.av ? w + m->off_eps() : nullptr,
+                         m->dm.av ? w + m->off_Q() : nullptr, st));
+    HIP_TRY(launch_residual(m->dm, scratch, st));
+    double scal[S_NSCAL];
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(scal, m->dm.scal, sizeof(scal), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&flag, m->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(m->time_collect());
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (stats) {
+        stats->steps = nsteps;
+        stats->status = flag ? DG_ENONFINITE : DG_OK;
+        stats->t = scal[S_T];
+        stats->dt_min = nsteps ? scal[S_DTMIN] : 0.0;
+        stats->dt_max = scal[S_DTMAX];
+        for (int c = 0; c < 4; ++c) {
+            stats->totals[c] = scal[S_TOT + c];
+            stats->residual[c] = scal[S_RES + c];
+        }
+        stats->wall_s = ms * 1e-3;
+        stats->dof_updates_per_s =
+            ms > 0 ? double(m->state_count()) * 5.0 * nsteps / (ms * 1e-3) : 0.0;
+    }
+    if (flag) return fail(DG_ENONFINITE, "state became non-finite or non-positive (rho or p)");
+    return DG_OK;
+}
+
+int dg_totals(dg_mesh *m, const void *U, double out[4], void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_totals(m->dm, U, st));
+    HIP_TRY(hipMemcpyAsync(out, m->dm.scal + S_TOT, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DG_OK;
+}
+
+int dg_residual(dg_mesh *m, const void *U, void *work, double out[4], void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(work, "work")) return rc;
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(work);
+    void *scratch = w + m->off_A();
+    if (m->dm.av) {
+        if (int rc = av_prepare(m, U, w, st)) return rc;
+    }
+    HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, scratch, 0, m->dm.av ? w + m->off_eps() : nullptr,
+                         m->dm.av ? w + m->off_Q() : nullptr, st));
+    HIP_TRY(launch_residual(m->dm, scratch, st));
+    HIP_TRY(hipMemcpyAsync(out, m->dm.scal + S_RES, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DG_OK;
+}
+
+int dg_viscosity(dg_mesh *m, const void *U, double *eps, void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (!m->dm.av) return fail(DG_EINVAL, "mesh was set up without artificial viscosity");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(eps, "eps")) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (m->dm.fp32) {
+        // state-precision scratch, then widen into the caller's doubles
+        if (!m->eps64_scratch) {
+            void *q = nullptr;
+            size_t bytes = align256(size_t(m->dm.K) * m->elem_bytes) + 2 * m->state_bytes();
+            if (hipMalloc(&q, bytes) != hipSuccess) return fail(DG_ENOMEM, "scratch allocation failed");
+            m->allocs.push_back(q);
+            m->eps64_scratch = static_cast<double *>(q);
+        }
+        HIP_TRY(launch_sensor(m->dm, U, m->eps64_scratch, st));
+        HIP_TRY(launch_eps_to_double(m->dm, m->eps64_scratch, eps, st));
+    } else {
+        HIP_TRY(launch_sensor(m->dm, U, eps, st));
+    }
+    return DG_OK;
+}
+
+int dg_set_kernel_timing(dg_mesh *m, int enable) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    m->timing = enable != 0;
+    return DG_OK;
+}
+
+int dg_kernel_time(dg_mesh *m, void *stream, double *stage_ms_total, long *stage_launches) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIP_TRY(m->time_collect());
+    if (stage_ms_total) *stage_ms_total = m->stage_ms;
+    if (stage_launches) *stage_launches = m->stage_launches;
+    m->stage_ms = 0.0;
+    m->stage_launches = 0;
+    return DG_OK;
+}
+
+int dg_status(dg_mesh *m, void *stream, int *device_flag) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (!device_flag) return fail(DG_EINVAL, "device_flag is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(device_flag, m->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Device-side helpers shared by the kernels: compile-time node tables,
+// packed connectivity, pointwise gas dynamics, numerical flux and boundary
+// states.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dg {
+
+constexpr int kFields = 4;  // rho, rho u, rho v, E
+
+template <int P>
+struct Order {
+    static constexpr int Np = (P + 1) * (P + 2) / 2;
+    static constexpr int Nfp = P + 1;
+    static constexpr int Nface = 3 * Nfp;
+    static constexpr int EW = 64 / Np;   // elements per wavefront
+    static constexpr int EB = 4 * EW;    // elements per 256-thread block
+};
+
+// Node id of face node j of face f.  Nodes are numbered in rows of constant
+// s (row n has P+1-n nodes), so face 0 is row 0, face 1 the last node of
+// each row (increasing s) and face 2 the first node of each row, taken from
+// the top row down (counter-clockwise).
+__host__ __device__ constexpr int row_start(int P, int n) { return n * (P + 1) - n * (n - 1) / 2; }
+
+__host__ __device__ constexpr int face_node(int P, int f, int j) {
+    return f == 0 ? j : (f == 1 ? row_start(P, j) + P - j : row_start(P, P - j));
+}
+
+template <int P>
+struct FaceTable {
+    int v[3 * (P + 1)];
+    constexpr FaceTable() : v() {
+        for (int f = 0; f < 3; ++f)
+            for (int j = 0; j < P + 1; ++j) v[f * (P + 1) + j] = face_node(P, f, j);
+    }
+};
+
+// Packed face information of an element: 4 bits per face, low 2 bits the
+// neighbour's face id, high 2 bits the boundary code.
+__host__ __device__ inline int face_nbr_face(int info, int f) { return (info >> (4 * f)) & 3; }
+__host__ __device__ inline int face_bc(int info, int f) { return (info >> (4 * f + 2)) & 3; }
+
+enum { BC_INTERIOR = 0, BC_WALL = 1, BC_FARFIELD = 2 };
+
+template <typename T>
+__device__ inline T pressure(T g, const T u[kFields]) {
+    return (g - T(1)) * (u[3] - T(0.5) * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+}
+
+// Normal flux n.F(u) and the wave speed |v.n| + c.
+template <typename T>
+__device__ inline void normal_flux(T g, const T u[kFields], T nx, T ny, T fn[kFields], T &lam) {
+    T ir = T(1) / u[0];
+    T vx = u[1] * ir, vy = u[2] * ir;
+    T p = pressure(g, u);
+    T vn = vx * nx + vy * ny;
+    fn[0] = u[0] * vn;
+    fn[1] = u[1] * vn + p * nx;
+    fn[2] = u[2] * vn + p * ny;
+    fn[3] = (u[3] + p) * vn;
+    lam = fabs(vn) + sqrt(g * p * ir);
+}
+
+// Boundary ghost state: slip-wall mirror or characteristic far field.
+template <typename T>
+__device__ inline void ghost_state(T g, int code, const T um[kFields], T nx, T ny,
+                                   const T qinf[kFields], T up[kFields]) {
+    if (code == BC_WALL) {
+        T mn = um[1] * nx + um[2] * ny;
+        up[0] = um[0];
+        up[1] = um[1] - T(2) * mn * nx;
+        up[2] = um[2] - T(2) * mn * ny;
+        up[3] = um[3];
+        return;
+    }
+    T rhoi = um[0], ui = um[1] / rhoi, vi = um[2] / rhoi;
+    T pi = pressure(g, um), ci = sqrt(g * pi / rhoi);
+    T vni = ui * nx + vi * ny;
+    T rhoo = qinf[0], uo = qinf[1] / rhoo, vo = qinf[2] / rhoo;
+    T po = pressure(g, qinf), co = sqrt(g * po / rhoo);
+    T vno = uo * nx + vo * ny;
+    if (vni <= -ci) {
+        for (int c = 0; c < kFields; ++c) up[c] = qinf[c];
+        return;
+    }
+    if (vni >= ci) {
+        for (int c = 0; c < kFields; ++c) up[c] = um[c];
+        return;
+    }
+    T gm1 = g - T(1);
+    T Rout = vni + T(2) * ci / gm1;
+    T Rin = vno - T(2) * co / gm1;
+    T vnb = T(0.5) * (Rout + Rin);
+    T cb = T(0.25) * gm1 * (Rout - Rin);
+    T sb, utb, vtb;
+    if (vnb > T(0)) {
+        sb = pi / pow(rhoi, g);
+        utb = ui - vni * nx;
+        vtb = vi - vni * ny;
+    } else {
+        sb = po / pow(rhoo, g);
+        utb = uo - vno * nx;
+        vtb = vo - vno * ny;
+    }
+    T rhob = pow(cb * cb / (g * sb), T(1) / gm1);
+    T pb = rhob * cb * cb / g;
+    T ub = utb + vnb * nx, vb = vtb + vnb * ny;
+    up[0] = rhob;
+    up[1] = rhob * ub;
+    up[2] = rhob * vb;
+    up[3] = pb / gm1 + T(0.5) * rhob * (ub * ub + vb * vb);
+}
+
+// n.F(u-) - F*(u-, u+) for the local Lax-Friedrichs flux
+// F* = (n.F(u-) + n.F(u+))/2 - lam (u+ - u-)/2, lam = max of the two local
+// wave speeds:  n.F(u-) - F* = (n.F(u-) - n.F(u+))/2 + lam (u+ - u-)/2.
+template <typename T>
+__device__ inline void lf_jump(T g, const T um[kFields], const T up[kFields], T nx, T ny,
+                               T d[kFields]) {
+    T fm[kFields], fp[kFields], lm, lp;
+    normal_flux(g, um, nx, ny, fm, lm);
+    normal_flux(g, up, nx, ny, fp, lp);
+    T lam = lm > lp ? lm : lp;
+    for (int c = 0; c < kFields; ++c) {
+        T fstar = T(0.5) * (fm[c] + fp[c]) - T(0.5) * lam * (up[c] - um[c]);
+        d[c] = fm[c] - fstar;
+    }
+}
+
+// Carpenter-Kennedy 2N-storage (5,4) coefficients.
+__host__ __device__ inline double rk_a(int s) {
+    switch (s) {
+        case 1: return -567301805773.0 / 1357537059087.0;
+        case 2: return -2404267990393.0 / 2016746695238.0;
+        case 3: return -3550918686646.0 / 2091501179385.0;
+        case 4: return -1275806237668.0 / 842570457699.0;
+        default: return 0.0;
+    }
+}
+__host__ __device__ inline double rk_b(int s) {
+    switch (s) {
+        case 0: return 1432997174477.0 / 9575080441755.0;
+        case 1: return 5161836677717.0 / 13612068292357.0;
+        case 2: return 1720146321549.0 / 2090206949498.0;
+        case 3: return 3134564353537.0 / 4481467310338.0;
+        default: return 2277821191437.0 / 14882151754819.0;
+    }
+}
+
+}  // namespace dg

@@ -1,0 +1,837 @@
+// HIP kernels of the nodal DG Euler solver for gfx950 (VALU path).
+//
+// Tiling: one 64-lane wavefront holds EW = floor(64/Np) whole elements, one
+// lane per node (lane = element * Np + node); a 256-thread block holds four
+// wavefronts.  Elements never straddle wavefronts.  The element's state,
+// fluxes and scaled face-flux jumps are staged in LDS; each lane keeps its
+// own rows of Dr, Ds and LIFT in registers and forms the contractions
+//   rhs_i = -(r_x (Dr F)_i + s_x (Ds F)_i + r_y (Dr G)_i + s_y (Ds G)_i)
+//           + sum_q LIFT_iq Fscale_q (n.F(U-) - F*)_q
+// (the semi-discrete system in nodal strong form), followed by the
+// low-storage Runge-Kutta update in the same kernel.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace dg {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+struct StageArgs {
+    int K, stage, mode;
+    T g, ra, rb;
+    T qinf[4];
+    const T *__restrict__ Uin;
+    T *__restrict__ Uout;
+    T *__restrict__ R;
+    T *__restrict__ rhs;
+    const int *__restrict__ nbr;
+    const int *__restrict__ finfo;
+    const T *__restrict__ geo;
+    const T *__restrict__ fgeo;
+    const T *__restrict__ ops;
+    const double *__restrict__ dt;
+    const T *__restrict__ eps;
+    const T *__restrict__ Q;
+};
+
+// Lane -> (local element, node) map shared by all element-tiled kernels.
+template <int P>
+struct Tile {
+    using O = Order<P>;
+    int lane, wave, le, i, el;
+    long k;
+    bool act;
+    __device__ Tile(int K) {
+        lane = threadIdx.x & 63;
+        wave = threadIdx.x >> 6;
+        le = lane / O::Np;
+        i = lane - le * O::Np;
+        bool lane_ok = le < O::EW;
+        el = lane_ok ? wave * O::EW + le : 0;
+        k = (long)blockIdx.x * O::EB + wave * O::EW + le;
+        act = lane_ok && k < K;
+    }
+};
+
+template <typename T, int P, bool AV>
+__global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
+    __shared__ T sU[EB][kFields][Np];
+    __shared__ T sF[EB][2 * kFields][Np];
+    __shared__ T sJ[EB][kFields][NF3];
+    Tile<P> t(a.K);
+    const long k = t.k;
+    const int i = t.i, el = t.el;
+
+    T u[kFields] = {};
+    T sig = T(0);
+    if (t.act) {
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) u[c] = a.Uin[(k * kFields + c) * Np + i];
+        T ir = T(1) / u[0];
+        T vx = u[1] * ir, vy = u[2] * ir;
+        T p = pressure(a.g, u);
+        T F[kFields] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
+        T G[kFields] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
+        if (AV) {
+            sig = sqrt(a.eps[k]);
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) {
+                F[c] -= sig * a.Q[((k * 2 + 0) * kFields + c) * Np + i];
+                G[c] -= sig * a.Q[((k * 2 + 1) * kFields + c) * Np + i];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) {
+            sU[el][c][i] = u[c];
+            sF[el][c][i] = F[c];
+            sF[el][kFields + c][i] = G[c];
+        }
+    }
+    __syncthreads();
+
+    if (t.act) {
+        const int info = a.finfo[k];
+        for (int q = i; q < NF3; q += Np) {
+            const int f = q / Nfp, j = q - f * Nfp;
+            const int vm = face_node(P, f, j);
+            T um[kFields], up[kFields], d[kFields];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) um[c] = sU[el][c][vm];
+            const T nx = a.fgeo[(k * 3 + 0) * NF3 + q];
+            const T ny = a.fgeo[(k * 3 + 1) * NF3 + q];
+            const T fs = a.fgeo[(k * 3 + 2) * NF3 + q];
+            const int code = face_bc(info, f);
+            long kn = -1;
+            int vp = 0;
+            if (code == BC_INTERIOR) {
+                kn = a.nbr[k * 3 + f];
+                vp = face_node(P, face_nbr_face(info, f), Nfp - 1 - j);
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) up[c] = a.Uin[(kn * kFields + c) * Np + vp];
+            } else {
+                ghost_state(a.g, code, um, nx, ny, a.qinf, up);
+            }
+            lf_jump(a.g, um, up, nx, ny, d);
+            if (AV) {
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) {
+                    T vmv = sig * (nx * a.Q[((k * 2 + 0) * kFields + c) * Np + vm] +
+                                   ny * a.Q[((k * 2 + 1) * kFields + c) * Np + vm]);
+                    T vstar = vmv;
+                    if (kn >= 0) {
+                        T sp = sqrt(a.eps[kn]);
+                        T vpv = sp * (nx * a.Q[((kn * 2 + 0) * kFields + c) * Np + vp] +
+                                      ny * a.Q[((kn * 2 + 1) * kFields + c) * Np + vp]);
+                        vstar = T(0.5) * (vmv + vpv);
+                    }
+                    d[c] += vstar - vmv;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) sJ[el][c][q] = fs * d[c];
+        }
+    }
+    __syncthreads();
+    if (!t.act) return;
+
+    T dr[Np], ds[Np], lf[NF3];
+#pragma unroll
+    for (int j = 0; j < Np; ++j) {
+        dr[j] = a.ops[i * Np + j];
+        ds[j] = a.ops[Np * Np + i * Np + j];
+    }
+#pragma unroll
+    for (int q = 0; q < NF3; ++q) lf[q] = a.ops[2 * Np * Np + i * NF3 + q];
+    const T rx = a.geo[(k * 4 + 0) * Np + i], sx = a.geo[(k * 4 + 1) * Np + i];
+    const T ry = a.geo[(k * 4 + 2) * Np + i], sy = a.geo[(k * 4 + 3) * Np + i];
+    const T dt = a.mode ? T(*a.dt) : T(0);
+#pragma unroll
+    for (int c = 0; c < kFields; ++c) {
+        T drf = 0, dsf = 0, drg = 0, dsg = 0;
+#pragma unroll
+        for (int j = 0; j < Np; ++j) {
+            const T fv = sF[el][c][j], gv = sF[el][kFields + c][j];
+            drf += dr[j] * fv;
+            dsf += ds[j] * fv;
+            drg += dr[j] * gv;
+            dsg += ds[j] * gv;
+        }
+        T val = -(rx * drf + sx * dsf + ry * drg + sy * dsg);
+#pragma unroll
+        for (int q = 0; q < NF3; ++q) val += lf[q] * sJ[el][c][q];
+        const long idx = (k * kFields + c) * Np + i;
+        if (a.mode == 0) {
+            a.rhs[idx] = val;
+        } else {
+            T r = (a.stage == 0) ? dt * val : a.ra * a.R[idx] + dt * val;
+            a.R[idx] = r;
+            a.Uout[idx] = u[c] + a.rb * r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// artificial viscosity
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct AvArgs {
+    int K, P;
+    T g;
+    T qinf[4];
+    double s0, kappa;
+    const T *__restrict__ U;
+    const T *__restrict__ eps_in;
+    T *__restrict__ eps_out;
+    T *__restrict__ Q;
+    const int *__restrict__ nbr;
+    const int *__restrict__ finfo;
+    const T *__restrict__ geo;
+    const T *__restrict__ fgeo;
+    const T *__restrict__ ops;
+    const T *__restrict__ emax;
+};
+
+// Persson-Peraire sensor on the density: u_hat = V^{-1} rho, S = (energy of
+// the degree-P modes) / (total modal energy), s = log10 S, sine ramp of
+// half-width kappa around s0, capped at eps_max,k.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp, EB = O::EB;
+    __shared__ T sR[EB][Np];
+    __shared__ double sE[EB][Np];
+    Tile<P> t(a.K);
+    if (t.act) sR[t.el][t.i] = a.U[(t.k * kFields + 0) * Np + t.i];
+    __syncthreads();
+    if (t.act) {
+        T uh = 0;
+#pragma unroll
+        for (int j = 0; j < Np; ++j) uh += a.ops[(2 * Np * Np + Np * 3 * Nfp) + t.i * Np + j] * sR[t.el][j];
+        sE[t.el][t.i] = double(uh) * double(uh);
+    }
+    __syncthreads();
+    if (t.act && t.i == 0) {
+        double num = 0, den = 0;
+#pragma unroll
+        for (int j = 0; j < Np; ++j) {
+            den += sE[t.el][j];
+            if (j >= Np - Nfp) num += sE[t.el][j];
+        }
+        double emax = double(a.emax[t.k]);
+        double e = 0.0;
+        if (den > 1e-300 && num > 0.0) {
+            double sk = log10(num / den);
+            if (sk > a.s0 + a.kappa)
+                e = emax;
+            else if (sk >= a.s0 - a.kappa)
+                e = 0.5 * emax * (1.0 + sin(M_PI * (sk - a.s0) / (2.0 * a.kappa)));
+        }
+        a.eps_out[t.k] = T(e);
+    }
+}
+
+// Auxiliary variable of the viscous system, q = sigma grad U (sigma =
+// sqrt eps_k), strong form with the central trace (sigma U)*:
+//   Q_x = sigma (r_x Dr U + s_x Ds U) + LIFT [Fscale n_x ((sigma U)* - sigma U-)]
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
+    __shared__ T sU[EB][kFields][Np];
+    __shared__ T sX[EB][kFields][NF3];
+    __shared__ T sY[EB][kFields][NF3];
+    Tile<P> t(a.K);
+    const long k = t.k;
+    const int i = t.i, el = t.el;
+    T sig = 0;
+    if (t.act) {
+        sig = sqrt(a.eps_in[k]);
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) sU[el][c][i] = a.U[(k * kFields + c) * Np + i];
+    }
+    __syncthreads();
+    if (t.act) {
+        const int info = a.finfo[k];
+        for (int q = i; q < NF3; q += Np) {
+            const int f = q / Nfp, j = q - f * Nfp;
+            const int vm = face_node(P, f, j);
+            T um[kFields], up[kFields];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) um[c] = sU[el][c][vm];
+            const T nx = a.fgeo[(k * 3 + 0) * NF3 + q];
+            const T ny = a.fgeo[(k * 3 + 1) * NF3 + q];
+            const T fs = a.fgeo[(k * 3 + 2) * NF3 + q];
+            const int code = face_bc(info, f);
+            T sp = sig;
+            if (code == BC_INTERIOR) {
+                const long kn = a.nbr[k * 3 + f];
+                const int vp = face_node(P, face_nbr_face(info, f), Nfp - 1 - j);
+                sp = sqrt(a.eps_in[kn]);
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) up[c] = a.U[(kn * kFields + c) * Np + vp];
+            } else {
+                ghost_state(a.g, code, um, nx, ny, a.qinf, up);
+            }
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) {
+                T star = T(0.5) * (sig * um[c] + sp * up[c]);
+                T d = fs * (star - sig * um[c]);
+                sX[el][c][q] = nx * d;
+                sY[el][c][q] = ny * d;
+            }
+        }
+    }
+    __syncthreads();
+    if (!t.act) return;
+    const T rx = a.geo[(k * 4 + 0) * Np + i], sx = a.geo[(k * 4 + 1) * Np + i];
+    const T ry = a.geo[(k * 4 + 2) * Np + i], sy = a.geo[(k * 4 + 3) * Np + i];
+#pragma unroll
+    for (int c = 0; c < kFields; ++c) {
+        T dru = 0, dsu = 0;
+#pragma unroll
+        for (int j = 0; j < Np; ++j) {
+            const T uv = sU[el][c][j];
+            dru += a.ops[i * Np + j] * uv;
+            dsu += a.ops[Np * Np + i * Np + j] * uv;
+        }
+        T qx = sig * (rx * dru + sx * dsu);
+        T qy = sig * (ry * dru + sy * dsu);
+#pragma unroll
+        for (int q = 0; q < NF3; ++q) {
+            const T l = a.ops[2 * Np * Np + i * NF3 + q];
+            qx += l * sX[el][c][q];
+            qy += l * sY[el][c][q];
+        }
+        a.Q[((k * 2 + 0) * kFields + c) * Np + i] = qx;
+        a.Q[((k * 2 + 1) * kFields + c) * Np + i] = qy;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// geometry (FP64, once per mesh)
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_geometry(int K, const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ ops,
+                                                     const double *__restrict__ Mref,
+                                                     double *__restrict__ geo,
+                                                     double *__restrict__ fgeo,
+                                                     double *__restrict__ wmass,
+                                                     double *__restrict__ emax, double av_eps0,
+                                                     int *__restrict__ count) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
+    __shared__ double sX[EB][Np], sY[EB][Np], sJ[EB][Np];
+    __shared__ double sM[EB][4][Np];  // xr, xs, yr, ys
+    __shared__ double sFs[EB][NF3];
+    Tile<P> t(K);
+    const long k = t.k;
+    const int i = t.i, el = t.el;
+    if (t.act) {
+        sX[el][i] = x[k * Np + i];
+        sY[el][i] = y[k * Np + i];
+    }
+    __syncthreads();
+    if (t.act) {
+        double xr = 0, xs = 0, yr = 0, ys = 0;
+        for (int j = 0; j < Np; ++j) {
+            const double dr = ops[i * Np + j], ds = ops[Np * Np + i * Np + j];
+            xr += dr * sX[el][j];
+            xs += ds * sX[el][j];
+            yr += dr * sY[el][j];
+            ys += ds * sY[el][j];
+        }
+        const double J = xr * ys - xs * yr;
+        if (!(J > 0.0)) atomicAdd(count, 1);
+        geo[(k * 4 + 0) * Np + i] = ys / J;
+        geo[(k * 4 + 1) * Np + i] = -yr / J;
+        geo[(k * 4 + 2) * Np + i] = -xs / J;
+        geo[(k * 4 + 3) * Np + i] = xr / J;
+        sJ[el][i] = J;
+        sM[el][0][i] = xr;
+        sM[el][1][i] = xs;
+        sM[el][2][i] = yr;
+        sM[el][3][i] = ys;
+    }
+    __syncthreads();
+    if (t.act) {
+        for (int q = i; q < NF3; q += Np) {
+            const int f = q / Nfp, j = q - f * Nfp;
+            const int v = face_node(P, f, j);
+            const double xr = sM[el][0][v], xs = sM[el][1][v], yr = sM[el][2][v], ys = sM[el][3][v];
+            double ax, ay;
+            if (f == 0) {
+                ax = yr;
+                ay = -xr;
+            } else if (f == 1) {
+                ax = ys - yr;
+                ay = xr - xs;
+            } else {
+                ax = -ys;
+                ay = xs;
+            }
+            const double len = sqrt(ax * ax + ay * ay);
+            fgeo[(k * 3 + 0) * NF3 + q] = ax / len;
+            fgeo[(k * 3 + 1) * NF3 + q] = ay / len;
+            const double fsc = len / sJ[el][v];
+            fgeo[(k * 3 + 2) * NF3 + q] = fsc;
+            sFs[el][q] = fsc;
+        }
+        double w = 0;
+        for (int j = 0; j < Np; ++j) w += Mref[i * Np + j] * sJ[el][j];
+        wmass[k * Np + i] = w;
+    }
+    __syncthreads();
+    if (t.act && i == 0) {
+        double fmax = 0;
+        for (int q = 0; q < NF3; ++q) fmax = fmax > sFs[el][q] ? fmax : sFs[el][q];
+        emax[k] = av_eps0 * (2.0 / fmax) / P;
+    }
+}
+
+template <int P>
+__global__ void k_check_normals(int K, const int *__restrict__ nbr, const int *__restrict__ finfo,
+                                const double *__restrict__ fgeo, int *__restrict__ count) {
+    constexpr int Nfp = P + 1, NF3 = 3 * Nfp;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)K * NF3) return;
+    const long k = gid / NF3;
+    const int q = int(gid - k * NF3);
+    const int f = q / Nfp, j = q - f * Nfp;
+    const int info = finfo[k];
+    if (face_bc(info, f) != BC_INTERIOR) return;
+    const long kn = nbr[k * 3 + f];
+    const int qn = face_nbr_face(info, f) * Nfp + Nfp - 1 - j;
+    const double ex = fgeo[(k * 3 + 0) * NF3 + q] + fgeo[(kn * 3 + 0) * NF3 + qn];
+    const double ey = fgeo[(k * 3 + 1) * NF3 + q] + fgeo[(kn * 3 + 1) * NF3 + qn];
+    if (!(fabs(ex) <= 1e-8 && fabs(ey) <= 1e-8)) atomicAdd(count + 1, 1);
+}
+
+__global__ void k_cast(const double *__restrict__ src, float *__restrict__ dst, size_t n) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) dst[g] = float(src[g]);
+}
+
+template <typename T>
+__global__ void k_eps_to_double(const T *__restrict__ src, double *__restrict__ dst, int n) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) dst[g] = double(src[g]);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: time step, totals, residual
+// ---------------------------------------------------------------------------
+
+// Fixed-shape tree reduction over the block (deterministic).
+template <typename Op>
+__device__ double block_reduce(double v, double *sh, Op op) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+struct MaxOp {
+    __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+struct SumOp {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+
+template <typename T, int P, bool AV>
+__global__ __launch_bounds__(kBlock) void k_cfl(int K, double g, const T *__restrict__ U,
+                                                const T *__restrict__ eps,
+                                                const double *__restrict__ fgeo64,
+                                                double *__restrict__ partial,
+                                                int *__restrict__ flag) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
+    __shared__ double sU[EB][kFields][Np];
+    __shared__ double sh[kBlock];
+    Tile<P> t(K);
+    const long k = t.k;
+    const int i = t.i, el = t.el;
+    int bad = 0;
+    if (t.act) {
+        double u[kFields];
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) {
+            u[c] = double(U[(k * kFields + c) * Np + i]);
+            sU[el][c][i] = u[c];
+        }
+        const double p = pressure(g, u);
+        if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+            !isfinite(p))
+            bad = 1;
+    }
+    __syncthreads();
+    double vmax = 0.0;
+    if (t.act) {
+        const double P1 = P + 1.0;
+        const double e = AV ? double(eps[k]) : 0.0;
+        for (int q = i; q < NF3; q += Np) {
+            const int f = q / Nfp, j = q - f * Nfp;
+            const int v = face_node(P, f, j);
+            double u[kFields];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) u[c] = sU[el][c][v];
+            const double vx = u[1] / u[0], vy = u[2] / u[0];
+            const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * pressure(g, u) / u[0]);
+            const double fs = fgeo64[(k * 3 + 2) * NF3 + q];
+            const double val = 0.5 * P1 * P1 * fs * lam + 0.25 * P1 * P1 * P1 * P1 * fs * fs * e;
+            if (val > vmax) vmax = val;
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+    const double r = block_reduce(vmax, sh, MaxOp());
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl_finish(int n, const double *__restrict__ partial,
+                                                       double cfl, double dt_fixed,
+                                                       double *__restrict__ scal) {
+    __shared__ double sh[kBlock];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < n; b += kBlock) v = v > partial[b] ? v : partial[b];
+    const double vmax = block_reduce(v, sh, MaxOp());
+    if (threadIdx.x == 0) {
+        const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * (1.0 / vmax);
+        scal[S_DT] = dt;
+        scal[S_T] += dt;
+        scal[S_DTMIN] = dt < scal[S_DTMIN] ? dt : scal[S_DTMIN];
+        scal[S_DTMAX] = dt > scal[S_DTMAX] ? dt : scal[S_DTMAX];
+        scal[S_STEPS] += 1.0;
+    }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_totals(int K, const T *__restrict__ U,
+                                                   const double *__restrict__ wmass,
+                                                   double *__restrict__ partial) {
+    using O = Order<P>;
+    constexpr int Np = O::Np;
+    __shared__ double sh[kBlock];
+    Tile<P> t(K);
+    double v[kFields] = {0, 0, 0, 0};
+    if (t.act) {
+        const double w = wmass[t.k * Np + t.i];
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) v[c] = w * double(U[(t.k * kFields + c) * Np + t.i]);
+    }
+#pragma unroll
+    for (int c = 0; c < kFields; ++c) {
+        const double r = block_reduce(v[c], sh, SumOp());
+        if (threadIdx.x == 0) partial[blockIdx.x * kFields + c] = r;
+    }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_absmax(int K, const T *__restrict__ X,
+                                                   double *__restrict__ partial) {
+    using O = Order<P>;
+    constexpr int Np = O::Np;
+    __shared__ double sh[kBlock];
+    Tile<P> t(K);
+    double v[kFields] = {0, 0, 0, 0};
+    if (t.act) {
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) v[c] = fabs(double(X[(t.k * kFields + c) * Np + t.i]));
+    }
+#pragma unroll
+    for (int c = 0; c < kFields; ++c) {
+        const double r = block_reduce(v[c], sh, MaxOp());
+        if (threadIdx.x == 0) partial[blockIdx.x * kFields + c] = r;
+    }
+}
+
+template <typename Op>
+__global__ __launch_bounds__(kBlock) void k_finish4(int n, const double *__restrict__ partial,
+                                                    double *__restrict__ out, Op op) {
+    __shared__ double sh[kBlock];
+    for (int c = 0; c < kFields; ++c) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < n; b += kBlock) v = op(v, partial[b * kFields + c]);
+        const double r = block_reduce(v, sh, op);
+        if (threadIdx.x == 0) out[c] = r;
+    }
+}
+
+__global__ void k_reset_scalars(double *scal) {
+    if (threadIdx.x == 0) {
+        for (int s = 0; s < S_NSCAL; ++s) scal[s] = 0.0;
+        scal[S_DTMIN] = DBL_MAX;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+
+template <int P>
+int nblocks(int K) {
+    return (K + Order<P>::EB - 1) / Order<P>::EB;
+}
+
+int nblocks_rt(int K, int P) {
+    switch (P) {
+        case 1: return nblocks<1>(K);
+        case 2: return nblocks<2>(K);
+        case 3: return nblocks<3>(K);
+        case 4: return nblocks<4>(K);
+        default: return nblocks<5>(K);
+    }
+}
+
+template <typename F>
+hipError_t with_order(int P, F &&f) {
+    switch (P) {
+        case 1: return f(std::integral_constant<int, 1>());
+        case 2: return f(std::integral_constant<int, 2>());
+        case 3: return f(std::integral_constant<int, 3>());
+        case 4: return f(std::integral_constant<int, 4>());
+        case 5: return f(std::integral_constant<int, 5>());
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+const T *tbl_geo(const DevMesh &m);
+template <>
+const double *tbl_geo<double>(const DevMesh &m) { return m.geo64; }
+template <>
+const float *tbl_geo<float>(const DevMesh &m) { return m.geo32; }
+template <typename T>
+const T *tbl_fgeo(const DevMesh &m);
+template <>
+const double *tbl_fgeo<double>(const DevMesh &m) { return m.fgeo64; }
+template <>
+const float *tbl_fgeo<float>(const DevMesh &m) { return m.fgeo32; }
+template <typename T>
+const T *tbl_ops(const DevMesh &m);
+template <>
+const double *tbl_ops<double>(const DevMesh &m) { return m.ops64; }
+template <>
+const float *tbl_ops<float>(const DevMesh &m) { return m.ops32; }
+template <typename T>
+const T *tbl_emax(const DevMesh &m);
+template <>
+const double *tbl_emax<double>(const DevMesh &m) { return m.emax64; }
+template <>
+const float *tbl_emax<float>(const DevMesh &m) { return m.emax32; }
+
+template <typename T>
+hipError_t stage_t(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                   const void *eps, const void *Q, hipStream_t st) {
+    StageArgs<T> a;
+    a.K = m.K;
+    a.stage = stage;
+    a.mode = rhs ? 0 : 1;
+    a.g = T(m.gamma);
+    a.ra = T(rk_a(stage));
+    a.rb = T(rk_b(stage));
+    for (int c = 0; c < 4; ++c) a.qinf[c] = T(m.qinf[c]);
+    a.Uin = static_cast<const T *>(Uin);
+    a.Uout = static_cast<T *>(Uout);
+    a.R = static_cast<T *>(R);
+    a.rhs = static_cast<T *>(rhs);
+    a.nbr = m.nbr;
+    a.finfo = m.finfo;
+    a.geo = tbl_geo<T>(m);
+    a.fgeo = tbl_fgeo<T>(m);
+    a.ops = tbl_ops<T>(m);
+    a.dt = m.scal + S_DT;
+    a.eps = static_cast<const T *>(eps);
+    a.Q = static_cast<const T *>(Q);
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        if (m.av)
+            hipLaunchKernelGGL((k_stage<T, P, true>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_stage<T, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+AvArgs<T> av_args(const DevMesh &m) {
+    AvArgs<T> a;
+    a.K = m.K;
+    a.P = m.P;
+    a.g = T(m.gamma);
+    for (int c = 0; c < 4; ++c) a.qinf[c] = T(m.qinf[c]);
+    a.s0 = m.av_s0;
+    a.kappa = m.av_kappa;
+    a.nbr = m.nbr;
+    a.finfo = m.finfo;
+    a.geo = tbl_geo<T>(m);
+    a.fgeo = tbl_fgeo<T>(m);
+    a.ops = tbl_ops<T>(m);
+    a.emax = tbl_emax<T>(m);
+    return a;
+}
+
+}  // namespace
+
+int partial_slots(int K, int P) { return nblocks_rt(K, P); }
+
+hipError_t launch_geometry(const DevMesh &m, const double *x, const double *y, double *geo64,
+                           double *fgeo64, double *wmass, double *emax64, double av_eps0,
+                           hipStream_t st) {
+    const double *Mref = m.ops64 + ops_size(m.Np, m.Nfp);
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_geometry<P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K, x, y,
+                           m.ops64, Mref, geo64, fgeo64, wmass, emax64, av_eps0, m.count);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_check_normals(const DevMesh &m, hipStream_t st) {
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        const long n = (long)m.K * 3 * (P + 1);
+        hipLaunchKernelGGL((k_check_normals<P>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           m.K, m.nbr, m.finfo, m.fgeo64, m.count);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                        const void *eps, const void *Q, hipStream_t st) {
+    return m.fp32 ? stage_t<float>(m, Uin, Uout, R, rhs, stage, eps, Q, st)
+                  : stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
+}
+
+template <typename T>
+static hipError_t sensor_t(const DevMesh &m, const void *U, void *eps, hipStream_t st) {
+    AvArgs<T> a = av_args<T>(m);
+    a.U = static_cast<const T *>(U);
+    a.eps_out = static_cast<T *>(eps);
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_sensor<T, P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_sensor(const DevMesh &m, const void *U, void *eps, hipStream_t st) {
+    return m.fp32 ? sensor_t<float>(m, U, eps, st) : sensor_t<double>(m, U, eps, st);
+}
+
+template <typename T>
+static hipError_t avgrad_t(const DevMesh &m, const void *U, const void *eps, void *Q, hipStream_t st) {
+    AvArgs<T> a = av_args<T>(m);
+    a.U = static_cast<const T *>(U);
+    a.eps_in = static_cast<const T *>(eps);
+    a.Q = static_cast<T *>(Q);
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_avgrad<T, P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_avgrad(const DevMesh &m, const void *U, const void *eps, void *Q, hipStream_t st) {
+    return m.fp32 ? avgrad_t<float>(m, U, eps, Q, st) : avgrad_t<double>(m, U, eps, Q, st);
+}
+
+template <typename T>
+static hipError_t cfl_t(const DevMesh &m, const void *U, const void *eps, double dt_fixed,
+                        hipStream_t st) {
+    hipError_t e = with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        if (m.av)
+            hipLaunchKernelGGL((k_cfl<T, P, true>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                               m.gamma, static_cast<const T *>(U), static_cast<const T *>(eps),
+                               m.fgeo64, m.partial, m.flag);
+        else
+            hipLaunchKernelGGL((k_cfl<T, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                               m.gamma, static_cast<const T *>(U), static_cast<const T *>(eps),
+                               m.fgeo64, m.partial, m.flag);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(kBlock), 0, st, nblocks_rt(m.K, m.P), m.partial,
+                       m.cfl, dt_fixed, m.scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const DevMesh &m, const void *U, const void *eps, double dt_fixed, hipStream_t st) {
+    return m.fp32 ? cfl_t<float>(m, U, eps, dt_fixed, st) : cfl_t<double>(m, U, eps, dt_fixed, st);
+}
+
+template <typename T>
+static hipError_t totals_t(const DevMesh &m, const void *U, hipStream_t st) {
+    hipError_t e = with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_totals<T, P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                           static_cast<const T *>(U), m.wmass, m.partial);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finish4<SumOp>, dim3(1), dim3(kBlock), 0, st, nblocks_rt(m.K, m.P), m.partial,
+                       m.scal + S_TOT, SumOp());
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(const DevMesh &m, const void *U, hipStream_t st) {
+    return m.fp32 ? totals_t<float>(m, U, st) : totals_t<double>(m, U, st);
+}
+
+template <typename T>
+static hipError_t residual_t(const DevMesh &m, const void *X, hipStream_t st) {
+    hipError_t e = with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_absmax<T, P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                           static_cast<const T *>(X), m.partial);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finish4<MaxOp>, dim3(1), dim3(kBlock), 0, st, nblocks_rt(m.K, m.P), m.partial,
+                       m.scal + S_RES, MaxOp());
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevMesh &m, const void *rhs, hipStream_t st) {
+    return m.fp32 ? residual_t<float>(m, rhs, st) : residual_t<double>(m, rhs, st);
+}
+
+hipError_t launch_eps_to_double(const DevMesh &m, const void *eps, double *out, hipStream_t st) {
+    const int n = m.K;
+    if (m.fp32)
+        hipLaunchKernelGGL((k_eps_to_double<float>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           st, static_cast<const float *>(eps), out, n);
+    else
+        hipLaunchKernelGGL((k_eps_to_double<double>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           st, static_cast<const double *>(eps), out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_scalars(const DevMesh &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(64), 0, st, m.scal);
+    return hipGetLastError();
+}
+
+}  // namespace dg

@@ -1,0 +1,86 @@
+// Interface between the C-ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace dg {
+
+// Slots of the per-mesh FP64 device scalars.
+enum Scalar {
+    S_DT = 0,       // step of the current/last step
+    S_T = 1,        // simulated time accumulated since the last reset
+    S_DTMIN = 2,
+    S_DTMAX = 3,
+    S_TOT = 4,      // 4 totals
+    S_RES = 8,      // 4 residuals
+    S_STEPS = 12,
+    S_NSCAL = 16
+};
+
+struct DevMesh {
+    int K = 0, P = 0, Np = 0, Nfp = 0;
+    bool fp32 = false;
+    bool av = false;
+    double gamma = 1.4, cfl = 0.5;
+    double qinf[4] = {1, 0, 0, 2.5};
+    double av_s0 = 0, av_kappa = 1;
+    const int *nbr = nullptr;      // [K][3] neighbour element
+    const int *finfo = nullptr;    // [K] packed neighbour face and bc codes
+    // FP64 tables
+    const double *geo64 = nullptr;   // [K][4][Np] rx, sx, ry, sy
+    const double *fgeo64 = nullptr;  // [K][3][3*Nfp] nx, ny, Fscale
+    const double *wmass = nullptr;   // [K][Np] mass weights w_ki = sum_j M_ij J_kj
+    const double *emax64 = nullptr;  // [K] eps_max per element
+    const double *ops64 = nullptr;   // Dr | Ds | LIFT | Vinv
+    // FP32 tables (FP32 handles)
+    const float *geo32 = nullptr, *fgeo32 = nullptr, *emax32 = nullptr, *ops32 = nullptr;
+    // device scalars and reduction scratch
+    double *scal = nullptr;   // [S_NSCAL]
+    int *flag = nullptr;      // non-finite / non-positive state flag
+    int *count = nullptr;     // setup counters (bad J, bad normals)
+    double *partial = nullptr;
+    int npartial = 0;
+};
+
+// offsets of the operators in the ops tables
+inline size_t ops_size(int Np, int Nfp) { return size_t(Np) * Np * 3 + size_t(Np) * 3 * Nfp; }
+inline size_t off_Dr(int, int) { return 0; }
+inline size_t off_Ds(int Np, int) { return size_t(Np) * Np; }
+inline size_t off_LIFT(int Np, int) { return size_t(2) * Np * Np; }
+inline size_t off_Vinv(int Np, int Nfp) { return size_t(2) * Np * Np + size_t(Np) * 3 * Nfp; }
+
+// number of partial-reduction slots the reduction kernels need
+int partial_slots(int K, int P);
+
+// setup: FP64 geometric factors from node coordinates (device x, y
+// [K][Np]); counts J <= 0 nodes into count[0].
+hipError_t launch_geometry(const DevMesh &m, const double *x, const double *y, double *geo64,
+                           double *fgeo64, double *wmass, double *emax64, double av_eps0,
+                           hipStream_t st);
+// counts interior face nodes whose normal is not minus the neighbour's into count[1]
+hipError_t launch_check_normals(const DevMesh &m, hipStream_t st);
+hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st);
+
+// rhs of state U (mode 0) or one LSERK stage (mode 1):
+//   R = a_s R + dt rhs (stage 0: R = dt rhs), Uout = Uin + b_s R.
+// eps: [K] viscosities and Q: [K][2][4][Np] gradients (AV only).
+hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
+                        int stage, const void *eps, const void *Q, hipStream_t st);
+// sensor: eps [K] (state precision) from U
+hipError_t launch_sensor(const DevMesh &m, const void *U, void *eps, hipStream_t st);
+// LDG auxiliary gradient Q from U and eps
+hipError_t launch_avgrad(const DevMesh &m, const void *U, const void *eps, void *Q, hipStream_t st);
+// CFL reduction -> scal[S_DT] (dt_fixed > 0 overrides), accumulates S_T,
+// S_DTMIN/MAX, S_STEPS; raises *flag on bad states.
+hipError_t launch_cfl(const DevMesh &m, const void *U, const void *eps, double dt_fixed,
+                      hipStream_t st);
+// conserved totals -> scal[S_TOT..]
+hipError_t launch_totals(const DevMesh &m, const void *U, hipStream_t st);
+// max |rhs| per field -> scal[S_RES..]
+hipError_t launch_residual(const DevMesh &m, const void *rhs, hipStream_t st);
+// eps (state precision) -> double
+hipError_t launch_eps_to_double(const DevMesh &m, const void *eps, double *out, hipStream_t st);
+hipError_t launch_reset_scalars(const DevMesh &m, hipStream_t st);
+
+}  // namespace dg

@@ -1,0 +1,287 @@
+"""Thin Python binding of ``libdg.so`` (the C ABI in ``include/dg.h``).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch provides device memory (``torch.Tensor.data_ptr()``)
+and the stream (``torch.cuda.current_stream().cuda_stream``).  Loading fails
+loudly if the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdg.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EGEOM, DG_ENONFINITE, DG_EDEVICE, DG_EBUSY = 0, -1, -2, -3, -4, -5, -6
+DG_FP64_PLAIN, DG_FP32 = 0, 2
+PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP32}
+
+# Every symbol include/dg.h declares.
+EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
+           "dg_reference_operators", "dg_mesh_setup", "dg_mesh_destroy", "dg_buffer_bytes",
+           "dg_rhs", "dg_step", "dg_run", "dg_totals", "dg_residual", "dg_viscosity",
+           "dg_set_kernel_timing", "dg_kernel_time", "dg_status")
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("K", C.c_int), ("P", C.c_int), ("precision", C.c_int),
+                ("gamma", C.c_double), ("cfl", C.c_double),
+                ("EToE", C.c_void_p), ("EToF", C.c_void_p), ("bc", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p),
+                ("freestream", C.c_double * 4),
+                ("av_enable", C.c_int), ("av_eps0", C.c_double), ("av_s0", C.c_double),
+                ("av_kappa", C.c_double)]
+
+
+class RunStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("status", C.c_int), ("t", C.c_double),
+                ("dt_min", C.c_double), ("dt_max", C.c_double),
+                ("totals", C.c_double * 4), ("residual", C.c_double * 4),
+                ("wall_s", C.c_double), ("dof_updates_per_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libdg.so`` (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1208_4772_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i, d = C.c_void_p, C.c_int, C.c_double
+        L.dg_last_error.restype = C.c_char_p
+        L.dg_version.restype = i
+        L.dg_reference_nodes.argtypes = [i, vp, vp]
+        L.dg_face_nodes.argtypes = [i, vp]
+        L.dg_reference_operators.argtypes = [i, vp, vp, vp, vp]
+        L.dg_mesh_setup.argtypes = [C.POINTER(MeshDesc), vp, C.POINTER(vp)]
+        L.dg_mesh_destroy.argtypes = [vp]
+        L.dg_buffer_bytes.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.dg_rhs.argtypes = [vp, vp, vp, d, vp]
+        L.dg_step.argtypes = [vp, vp, vp, d, vp]
+        L.dg_run.argtypes = [vp, vp, vp, i, C.POINTER(RunStats), vp]
+        L.dg_totals.argtypes = [vp, vp, vp, vp]
+        L.dg_residual.argtypes = [vp, vp, vp, vp, vp]
+        L.dg_viscosity.argtypes = [vp, vp, vp, vp]
+        L.dg_status.argtypes = [vp, vp, C.POINTER(i)]
+        L.dg_set_kernel_timing.argtypes = [vp, i]
+        L.dg_kernel_time.argtypes = [vp, vp, C.POINTER(d), C.POINTER(C.c_long)]
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype or i
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != DG_OK:
+        msg = lib().dg_last_error().decode(errors="replace")
+        raise DGError(rc, msg)
+    return rc
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def n_nodes(P):
+    return (P + 1) * (P + 2) // 2
+
+
+def reference_nodes(P: int):
+    Np = n_nodes(P)
+    r = np.zeros(Np)
+    s = np.zeros(Np)
+    _check(lib().dg_reference_nodes(P, _p(r), _p(s)))
+    return r, s
+
+
+def face_nodes(P: int):
+    fm = np.zeros(3 * (P + 1), dtype=np.int32)
+    _check(lib().dg_face_nodes(P, _p(fm)))
+    return fm.reshape(3, P + 1)
+
+
+def reference_operators(P: int):
+    Np, Nfp = n_nodes(P), P + 1
+    Dr = np.zeros((Np, Np))
+    Ds = np.zeros((Np, Np))
+    LIFT = np.zeros((Np, 3 * Nfp))
+    Vinv = np.zeros((Np, Np))
+    _check(lib().dg_reference_operators(P, _p(Dr), _p(Ds), _p(LIFT), _p(Vinv)))
+    return dict(Dr=Dr, Ds=Ds, LIFT=LIFT, Vinv=Vinv)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Stats:
+    steps: int
+    status: int
+    t: float
+    dt_min: float
+    dt_max: float
+    totals: tuple
+    residual: tuple
+    wall_s: float
+    dof_updates_per_s: float
+
+
+class Solver:
+    """One mesh on one GPU.  States are torch tensors (K, 4, Np) on the
+    device in the handle's precision (float64 for ``fp64``, float32 for
+    ``fp32``)."""
+
+    def __init__(self, EToE, EToF, bc, x, y, P, precision="fp32", gamma=1.4, cfl=0.5,
+                 freestream=(1.0, 0.0, 0.0, 2.5), av=False, av_eps0=0.3, av_s0=float("nan"),
+                 av_kappa=1.0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.P = int(P)
+        self.Np = n_nodes(self.P)
+        self.precision = precision
+        self.dtype = torch.float32 if PRECISIONS[precision] == DG_FP32 else torch.float64
+        self._keep = [np.ascontiguousarray(EToE, dtype=np.int32),
+                      np.ascontiguousarray(EToF, dtype=np.int32),
+                      np.ascontiguousarray(bc, dtype=np.int8),
+                      np.ascontiguousarray(x, dtype=np.float64),
+                      np.ascontiguousarray(y, dtype=np.float64)]
+        e2e, e2f, b, xx, yy = self._keep
+        self.K = int(e2e.shape[0])
+        assert xx.shape == (self.K, self.Np) and yy.shape == (self.K, self.Np)
+        d = MeshDesc()
+        d.K, d.P, d.precision = self.K, self.P, PRECISIONS[precision]
+        d.gamma, d.cfl = gamma, cfl
+        d.EToE, d.EToF, d.bc = _p(e2e).value, _p(e2f).value, _p(b).value
+        d.x, d.y = _p(xx).value, _p(yy).value
+        for c in range(4):
+            d.freestream[c] = float(freestream[c])
+        d.av_enable = 1 if av else 0
+        d.av_eps0 = av_eps0
+        d.av_s0 = av_s0 if av_s0 is not None else float("nan")
+        d.av_kappa = av_kappa
+        self.av = bool(av)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().dg_mesh_setup(C.byref(d), _stream_handle(), C.byref(self._h)))
+        sb, wb = C.c_size_t(), C.c_size_t()
+        _check(lib().dg_buffer_bytes(self._h, C.byref(sb), C.byref(wb)))
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+        self.work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
+
+    @classmethod
+    def from_case(cls, case, precision="fp32", x=None, y=None, **kw):
+        """Solver for a :class:`meshgen.cases.Case` (its x, y unless given)."""
+        m = case.mesh
+        args = dict(gamma=case.gamma, cfl=case.cfl, freestream=case.freestream, av=case.av,
+                    av_eps0=case.av_eps0, av_kappa=case.av_kappa, av_s0=case.av_s0)
+        args.update(kw)
+        return cls(m.EToE, m.EToF, m.bc, case.x if x is None else x, case.y if y is None else y,
+                   case.P, precision, **args)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dg_mesh_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- states -------------------------------------------------------------
+    def state(self, U_host):
+        """Device state from a host float64 array (K, 4, Np)."""
+        t = self.torch.as_tensor(np.ascontiguousarray(U_host, dtype=np.float64))
+        assert tuple(t.shape) == (self.K, 4, self.Np)
+        return t.to(self.device).to(self.dtype).contiguous()
+
+    def empty_state(self):
+        return self.torch.empty((self.K, 4, self.Np), dtype=self.dtype, device=self.device)
+
+    def _check_state(self, U):
+        if U.dtype != self.dtype or not U.is_contiguous() or tuple(U.shape) != (self.K, 4, self.Np):
+            raise ValueError(f"state must be a contiguous {self.dtype} tensor of shape "
+                             f"{(self.K, 4, self.Np)}")
+        if U.device != self.device:
+            raise ValueError(f"state must live on {self.device}")
+
+    # -- solver calls -------------------------------------------------------
+    def rhs(self, U, out=None, stream=None):
+        self._check_state(U)
+        out = self.empty_state() if out is None else out
+        self._check_state(out)
+        _check(lib().dg_rhs(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(out.data_ptr()), 0.0,
+                            _stream_handle(stream)))
+        return out
+
+    def step(self, U, dt=0.0, stream=None):
+        self._check_state(U)
+        _check(lib().dg_step(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                             float(dt), _stream_handle(stream)))
+        return U
+
+    def run(self, U, nsteps, stream=None, check=True):
+        self._check_state(U)
+        st = RunStats()
+        rc = lib().dg_run(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                          int(nsteps), C.byref(st), _stream_handle(stream))
+        if check:
+            _check(rc)
+        return Stats(st.steps, st.status, st.t, st.dt_min, st.dt_max, tuple(st.totals),
+                     tuple(st.residual), st.wall_s, st.dof_updates_per_s)
+
+    def totals(self, U, stream=None):
+        self._check_state(U)
+        out = np.zeros(4)
+        _check(lib().dg_totals(self._h, C.c_void_p(U.data_ptr()), _p(out), _stream_handle(stream)))
+        return out
+
+    def residual(self, U, stream=None):
+        self._check_state(U)
+        out = np.zeros(4)
+        _check(lib().dg_residual(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                                 _p(out), _stream_handle(stream)))
+        return out
+
+    def viscosity(self, U, stream=None):
+        self._check_state(U)
+        eps = self.torch.empty(self.K, dtype=self.torch.float64, device=self.device)
+        _check(lib().dg_viscosity(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(eps.data_ptr()),
+                                  _stream_handle(stream)))
+        return eps
+
+    def set_kernel_timing(self, enable=True):
+        _check(lib().dg_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self, stream=None):
+        """(total ms, launches) of the stage kernel since the last call."""
+        ms, n = C.c_double(0), C.c_long(0)
+        _check(lib().dg_kernel_time(self._h, _stream_handle(stream), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def status(self, stream=None):
+        f = C.c_int(0)
+        _check(lib().dg_status(self._h, _stream_handle(stream), C.byref(f)))
+        return f.value
+
+    def dofs(self):
+        return 4 * self.Np * self.K

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Bars: FP64 path within 1e-12 relative L2 of the oracle (rhs and 100-step
+runs); FP32 path within the bound derived from FP32 rounding of the
+contractions (FP32_RHS_TOL, FP32_RUN_TOL below), with the measured errors
+printed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import meshgen
+from oracle import oracle as orc
+from oracle.refelem import ref
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32: unit roundoff 6e-8 times the cancellation in the flux derivatives
+# (|Dr| |F| / |Dr F| of order 10-100 on these meshes); see the derivation
+# next to the parity bars in the design notes.
+FP32_RHS_TOL = 2e-5
+FP32_RUN_TOL = 2e-5
+
+
+def dg():
+    from paper_1208_4772_amd import dg as _dg
+    return _dg
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def perturbed_state(x, y, q, amp=0.1):
+    """Smooth perturbation of the state q (rho, rho u, rho v, E)."""
+    rho0, u0, v0 = q[0], q[1] / q[0], q[2] / q[0]
+    p0 = 0.4 * (q[3] - 0.5 * rho0 * (u0 * u0 + v0 * v0))
+    rho = rho0 * (1 + amp * np.sin(x) * np.cos(0.7 * y))
+    u = u0 + amp * np.sin(0.9 * y)
+    v = v0 + amp * np.cos(1.1 * x)
+    p = p0 * (1 + amp * np.cos(x + 0.5 * y))
+    return meshgen.primitive_to_conserved(rho, u, v, p)
+
+
+def case_pair(mesh, P, q, precision, av=False, **kw):
+    R = ref(P)
+    x, y = meshgen.node_coordinates(mesh, R.r, R.s)
+    o = orc.Oracle(mesh, P, x, y, freestream=q, av=av, **kw)
+    s = dg().Solver(mesh.EToE, mesh.EToF, mesh.bc, x, y, P, precision, freestream=q, av=av,
+                    **{k: v for k, v in kw.items() if k in ("cfl", "av_eps0", "av_kappa", "av_s0")})
+    return o, s, x, y
+
+
+def meshes_for_rhs():
+    qv = np.array([1.0, 1.0, 0.0, 1.0 / 0.4 + 0.5])
+    out = []
+    for P in (1, 2, 3, 4, 5):
+        out.append((f"curved_periodic_P{P}", lambda: meshgen.periodic_square(5, perm_seed=11, curved_amplitude=0.05), P, qv))
+    out.append(("vortex_config_P2", lambda: meshgen.periodic_square(16), 2, qv))
+    out.append(("ragged_P5_K18", lambda: meshgen.periodic_square(3, perm_seed=5), 5, qv))
+    out.append(("cylinder_small_P4", lambda: meshgen.cylinder_annulus(24, 6), 4, meshgen.freestream_state(0.38)))
+    out.append(("farfield_annulus_P3", lambda: meshgen.cylinder_annulus(20, 5, inner_bc=meshgen.BC_FARFIELD), 3,
+                meshgen.freestream_state(0.5, 5.0)))
+    out.append(("airfoil_small_P3", lambda: meshgen.naca4_ogrid(40, 8), 3, meshgen.freestream_state(0.8, 1.25)))
+    return out
+
+
+@pytest.mark.parametrize("name,mk,P,q", meshes_for_rhs(), ids=[m[0] for m in meshes_for_rhs()])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rhs_matches_oracle(name, mk, P, q, precision):
+    import torch
+    mesh = mk()
+    o, s, x, y = case_pair(mesh, P, q, precision)
+    U = perturbed_state(x, y, q)
+    ref_rhs = o.rhs(U)
+    got = s.rhs(s.state(U)).double().cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(got, ref_rhs)
+    print(f"[{name} {precision}] K={mesh.K} rel L2 {err:.3e} max {np.abs(got - ref_rhs).max():.3e}")
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_RHS_TOL)
+
+
+def test_single_element_all_walls():
+    """K = 1: one triangle whose three faces are slip walls."""
+    VX = np.array([0.0, 1.0, 0.2])
+    VY = np.array([0.0, 0.1, 0.9])
+    m = meshgen.Mesh(VX, VY, np.array([[0, 1, 2]]), np.zeros((1, 3), np.int32),
+                     np.array([[0, 1, 2]], np.int32), np.ones((1, 3), np.int8))
+    q = meshgen.freestream_state(0.3)
+    for P in (1, 3, 5):
+        o, s, x, y = case_pair(m, P, q, "fp64")
+        U = perturbed_state(x, y, q)
+        got = s.rhs(s.state(U)).cpu().numpy()
+        assert rel_l2(got, o.rhs(U)) <= FP64_TOL
+
+
+def test_run_fp64_vortex_config_100_steps():
+    """512 jittered, permuted triangles, P=2, isentropic vortex, CFL 0.5,
+    100 CFL steps: state, time and totals against the oracle."""
+    P = 2
+    R = ref(P)
+    case = meshgen.make_case("vortex", R.r, R.s)
+    o = orc.Oracle.for_case(case)
+    s = dg().Solver.from_case(case, "fp64")
+    Ur, info = o.run(case.U0, case.steps)
+    Ud = s.state(case.U0)
+    st = s.run(Ud, case.steps)
+    got = Ud.cpu().numpy()
+    err = rel_l2(got, Ur)
+    print(f"[vortex fp64] rel L2 {err:.3e} t {st.t} vs {info['t']}")
+    assert err <= FP64_TOL
+    assert abs(st.t - info["t"]) <= 1e-12 * info["t"]
+    assert abs(st.dt_min - info["dt_min"]) <= 1e-12 * info["dt_min"]
+    np.testing.assert_allclose(st.totals, o.totals(Ur), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(s.totals(Ud), o.totals(Ur), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(st.residual, o.residual(Ur), rtol=1e-10, atol=1e-12)
+    assert st.status == 0
+
+
+def test_run_fp32_vortex_config_100_steps():
+    P = 2
+    R = ref(P)
+    case = meshgen.make_case("vortex", R.r, R.s)
+    o = orc.Oracle.for_case(case)
+    s = dg().Solver.from_case(case, "fp32")
+    Ur, info = o.run(case.U0, case.steps)
+    Ud = s.state(case.U0)
+    st = s.run(Ud, case.steps)
+    got = Ud.double().cpu().numpy()
+    err = rel_l2(got, Ur)
+    mx = np.abs(got - Ur).max()
+    print(f"[vortex fp32] rel L2 {err:.3e} max {mx:.3e} t {st.t} vs {info['t']}")
+    assert err <= FP32_RUN_TOL
+    assert abs(st.t - info["t"]) <= 1e-5 * info["t"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fixed_dt_steps_match_oracle(precision):
+    mesh = meshgen.cylinder_annulus(24, 6)
+    q = meshgen.freestream_state(0.38)
+    o, s, x, y = case_pair(mesh, 4, q, precision)
+    U = perturbed_state(x, y, q, amp=0.02)
+    Ur, _ = o.run(U, 3, dt=1e-3)
+    Ud = s.state(U)
+    for _ in range(3):
+        s.step(Ud, dt=1e-3)
+    got = Ud.double().cpu().numpy()
+    err = rel_l2(got, Ur)
+    print(f"[fixed dt {precision}] rel L2 {err:.3e}")
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_RUN_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bench_config_full_size(precision):
+    """The benchmark workload at full size (cylinder, 20,000 curved-wall
+    triangles, P=4, slip wall + far field): rhs of a perturbed state over all
+    20,000 elements, and 10 CFL steps from the impulsive freestream start."""
+    R = ref(4)
+    case = meshgen.make_case("cylinder", R.r, R.s)
+    assert case.K == 20000
+    o = orc.Oracle.for_case(case)
+    s = dg().Solver.from_case(case, precision)
+    U = perturbed_state(case.x, case.y, case.freestream, amp=0.05)
+    got = s.rhs(s.state(U)).double().cpu().numpy()
+    err = rel_l2(got, o.rhs(U))
+    print(f"[cylinder full rhs {precision}] rel L2 {err:.3e}")
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_RHS_TOL)
+    Ur, info = o.run(case.U0, 10)
+    Ud = s.state(case.U0)
+    st = s.run(Ud, 10)
+    got = Ud.double().cpu().numpy()
+    # compare the change from the start (the state itself is dominated by
+    # the uniform freestream)
+    err = rel_l2(got - case.U0, Ur - case.U0)
+    print(f"[cylinder full 10 steps {precision}] rel L2 of the update {err:.3e}")
+    assert err <= (FP64_TOL * 10 if precision == "fp64" else 1e-3)
+    assert abs(st.t - info["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * info["t"]
+
+
+def test_viscosity_and_av_rhs_match_oracle():
+    mesh = meshgen.naca4_ogrid(40, 8)
+    q = meshgen.freestream_state(0.8, 1.25)
+    P = 3
+    o, s, x, y = case_pair(mesh, P, q, "fp64", av=True, av_kappa=1.0, av_eps0=0.3)
+    U = perturbed_state(x, y, q, amp=0.02)
+    # a density step across x = 0.4 triggers the sensor near the airfoil
+    U[:, 0] *= np.where(x < 0.4, 1.0, 2.5)
+    U[:, 3] *= np.where(x < 0.4, 1.0, 2.5)
+    eps_ref = o.sensor(U)
+    eps = s.viscosity(s.state(U)).cpu().numpy()
+    assert (eps_ref > 0).sum() > 0
+    np.testing.assert_allclose(eps, eps_ref, rtol=0, atol=1e-12 * eps_ref.max())
+    got = s.rhs(s.state(U)).cpu().numpy()
+    err = rel_l2(got, o.rhs(U))
+    print(f"[airfoil AV rhs fp64] rel L2 {err:.3e}, {int((eps_ref > 0).sum())} viscous elements")
+    assert err <= FP64_TOL
+
+
+def test_clockwise_element_is_a_geometry_error():
+    m = meshgen.periodic_square(4, perm_seed=None)
+    m.EToV[0, 1], m.EToV[0, 2] = m.EToV[0, 2], m.EToV[0, 1]
+    R = ref(2)
+    x, y = meshgen.node_coordinates(m, R.r, R.s)
+    with pytest.raises(dg().DGError) as e:
+        dg().Solver(m.EToE, m.EToF, m.bc, x, y, 2, "fp64")
+    assert e.value.code == dg().DG_EGEOM
+
+
+def test_nonfinite_state_is_reported():
+    P = 2
+    R = ref(P)
+    case = meshgen.make_case("vortex", R.r, R.s)
+    s = dg().Solver.from_case(case, "fp32")
+    U = case.U0.copy()
+    U[7, 0, 3] = -1.0   # negative density
+    Ud = s.state(U)
+    with pytest.raises(dg().DGError) as e:
+        s.run(Ud, 1)
+    assert e.value.code == dg().DG_ENONFINITE
+
+
+def test_runs_are_bitwise_deterministic():
+    P = 4
+    R = ref(P)
+    case = meshgen.make_case("cylinder", R.r, R.s, scale=0.05)
+    s = dg().Solver.from_case(case, "fp32")
+    a = s.state(case.U0)
+    b = s.state(case.U0)
+    s.run(a, 20)
+    s.run(b, 20)
+    assert bool((a == b).all())
