@@ -289,6 +289,42 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         dm.fgeo32 = fgeo32;
         dm.emax32 = emax32;
         dm.ops32 = ops32;
+        // matrix-core kernel tables: packed connectivity, affine records for
+        // every element, per-node records for curved ones, A operand
+        int *conn4_d, *cidx_d, *flags_d;
+        float *geoA_d, *opsA_d;
+        const size_t nA = mfma_opsA_floats(P);
+        if ((rc = m->alloc(&conn4_d, size_t(K) * 4)) || (rc = m->alloc(&cidx_d, size_t(K))) ||
+            (rc = m->alloc(&flags_d, size_t(K))) || (rc = m->alloc(&geoA_d, size_t(K) * 16)) ||
+            (rc = m->alloc(&opsA_d, nA)))
+            return cleanup(rc);
+        std::vector<int> conn4(size_t(K) * 4);
+        for (long k = 0; k < K; ++k) {
+            conn4[k * 4 + 0] = nbr[k * 3 + 0];
+            conn4[k * 4 + 1] = nbr[k * 3 + 1];
+            conn4[k * 4 + 2] = nbr[k * 3 + 2];
+            conn4[k * 4 + 3] = finfo[k];
+        }
+        std::vector<float> opsA(nA);
+        mfma_fill_opsA(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsA.data());
+        SETUP_TRY(hipMemcpyAsync(conn4_d, conn4.data(), sizeof(int) * conn4.size(), hipMemcpyHostToDevice, st));
+        SETUP_TRY(hipMemcpyAsync(opsA_d, opsA.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
+        SETUP_TRY(launch_affine_flags(dm, flags_d, st));
+        std::vector<int> flags(K), cidx(K);
+        SETUP_TRY(hipMemcpyAsync(flags.data(), flags_d, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+        SETUP_TRY(hipStreamSynchronize(st));
+        int Kc = 0;
+        for (long k = 0; k < K; ++k) cidx[k] = flags[k] ? -1 : Kc++;
+        float *geoC_d;
+        if ((rc = m->alloc(&geoC_d, size_t(Kc) * (4 * Np + 9 * Nfp)))) return cleanup(rc);
+        SETUP_TRY(hipMemcpyAsync(cidx_d, cidx.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        SETUP_TRY(launch_pack_geometry(dm, cidx_d, geoA_d, geoC_d, st));
+        dm.conn4 = conn4_d;
+        dm.cidx = cidx_d;
+        dm.geoA = geoA_d;
+        dm.geoC = geoC_d;
+        dm.opsA = opsA_d;
+        dm.Kc = Kc;
         SETUP_TRY(hipStreamSynchronize(st));
     }
     *out = m;

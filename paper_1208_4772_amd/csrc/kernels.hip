@@ -418,6 +418,52 @@ __global__ void k_check_normals(int K, const int *__restrict__ nbr, const int *_
     if (!(fabs(ex) <= 1e-8 && fabs(ey) <= 1e-8)) atomicAdd(count + 1, 1);
 }
 
+template <int P>
+__global__ void k_affine_flags(int K, const double *__restrict__ geo, const double *__restrict__ fgeo,
+                               int *__restrict__ flags) {
+    constexpr int Np = (P + 1) * (P + 2) / 2, Nfp = P + 1, NF3 = 3 * Nfp;
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    bool affine = true;
+    for (int m = 0; m < 4; ++m) {
+        const double *g = geo + (k * 4 + m) * Np;
+        double scale = 0;
+        for (int i = 0; i < Np; ++i) scale = fmax(scale, fabs(g[i]));
+        for (int i = 1; i < Np; ++i) affine &= fabs(g[i] - g[0]) <= 1e-10 * scale;
+    }
+    for (int m = 0; m < 3; ++m) {
+        const double *g = fgeo + (k * 3 + m) * NF3;
+        for (int f = 0; f < 3; ++f) {
+            const double ref = g[f * Nfp];
+            const double scale = m == 2 ? fabs(ref) : 1.0;
+            for (int j = 1; j < Nfp; ++j) affine &= fabs(g[f * Nfp + j] - ref) <= 1e-10 * scale;
+        }
+    }
+    flags[k] = affine ? 1 : 0;
+}
+
+template <int P>
+__global__ void k_pack_geometry(int K, const double *__restrict__ geo, const double *__restrict__ fgeo,
+                                const int *__restrict__ cidx, float *__restrict__ geoA,
+                                float *__restrict__ geoC) {
+    constexpr int Np = (P + 1) * (P + 2) / 2, Nfp = P + 1, NF3 = 3 * Nfp;
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    float *ga = geoA + k * 16;
+    for (int m = 0; m < 4; ++m) ga[m] = float(geo[(k * 4 + m) * Np]);
+    for (int f = 0; f < 3; ++f)
+        for (int m = 0; m < 3; ++m) ga[4 + 3 * f + m] = float(fgeo[(k * 3 + m) * NF3 + f * Nfp]);
+    ga[13] = ga[14] = ga[15] = 0.f;
+    const int c = cidx[k];
+    if (c >= 0) {
+        float *gc = geoC + (long)c * (4 * Np + 9 * Nfp);
+        for (int m = 0; m < 4; ++m)
+            for (int i = 0; i < Np; ++i) gc[m * Np + i] = float(geo[(k * 4 + m) * Np + i]);
+        for (int m = 0; m < 3; ++m)
+            for (int q = 0; q < NF3; ++q) gc[4 * Np + m * NF3 + q] = float(fgeo[(k * 3 + m) * NF3 + q]);
+    }
+}
+
 __global__ void k_cast(const double *__restrict__ src, float *__restrict__ dst, size_t n) {
     const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < n) dst[g] = float(src[g]);
@@ -712,6 +758,25 @@ hipError_t launch_check_normals(const DevMesh &m, hipStream_t st) {
     });
 }
 
+hipError_t launch_affine_flags(const DevMesh &m, int *flags, hipStream_t st) {
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_affine_flags<P>), dim3((m.K + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           m.K, m.geo64, m.fgeo64, flags);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pack_geometry(const DevMesh &m, const int *cidx, float *geoA, float *geoC,
+                                hipStream_t st) {
+    return with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_pack_geometry<P>), dim3((m.K + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           m.K, m.geo64, m.fgeo64, cidx, geoA, geoC);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cast, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, dst, n);
@@ -720,6 +785,7 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) 
 
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                         const void *eps, const void *Q, hipStream_t st) {
+    if (m.fp32 && !m.av) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, st);
     return m.fp32 ? stage_t<float>(m, Uin, Uout, R, rhs, stage, eps, Q, st)
                   : stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }

@@ -35,6 +35,13 @@ struct DevMesh {
     const double *ops64 = nullptr;   // Dr | Ds | LIFT | Vinv
     // FP32 tables (FP32 handles)
     const float *geo32 = nullptr, *fgeo32 = nullptr, *emax32 = nullptr, *ops32 = nullptr;
+    // FP32 matrix-core stage kernel tables
+    const int *conn4 = nullptr;     // [K][4] nbr0, nbr1, nbr2, packed face info
+    const float *geoA = nullptr;    // [K][16] affine geometry record
+    const int *cidx = nullptr;      // [K] curved slot or -1
+    const float *geoC = nullptr;    // [Kc][4 Np + 9 Nfp] curved geometry
+    const float *opsA = nullptr;    // MFMA A operand table
+    int Kc = 0;
     // device scalars and reduction scratch
     double *scal = nullptr;   // [S_NSCAL]
     int *flag = nullptr;      // non-finite / non-positive state flag
@@ -67,6 +74,20 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st);
 // eps: [K] viscosities and Q: [K][2][4][Np] gradients (AV only).
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
                         int stage, const void *eps, const void *Q, hipStream_t st);
+// FP32 matrix-core stage kernel (no artificial viscosity)
+hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
+                             int stage, hipStream_t st);
+size_t mfma_opsA_floats(int P);
+void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out);
+int mfma_elements_per_block(int P);
+// setup: flags[k] = 1 if element k's metric terms, normals and Fscale are
+// constant to 1e-10 relative (a straight element)
+hipError_t launch_affine_flags(const DevMesh &m, int *flags, hipStream_t st);
+// setup: pack the affine records of all elements and the per-node records
+// of curved ones (cidx >= 0) from the FP64 tables
+hipError_t launch_pack_geometry(const DevMesh &m, const int *cidx, float *geoA, float *geoC,
+                                hipStream_t st);
+
 // sensor: eps [K] (state precision) from U
 hipError_t launch_sensor(const DevMesh &m, const void *U, void *eps, hipStream_t st);
 // LDG auxiliary gradient Q from U and eps
