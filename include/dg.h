@@ -164,6 +164,13 @@ int dg_residual(dg_mesh *mesh, const void *U, void *work, double out[4], void *s
  * only.  Returns DG_EINVAL if the mesh was set up without viscosity. */
 int dg_viscosity(dg_mesh *mesh, const void *U, double *eps, void *stream);
 
+/* Replay of captured steps.  With graphs enabled (the default), dg_run on
+ * an FP32 handle without artificial viscosity captures two steps into a
+ * hipGraph once per (U, work) pair and replays it, which removes per-launch
+ * host overhead; the arithmetic is identical to the eager launches.  Graphs
+ * are not used while kernel timing is enabled. */
+int dg_set_graphs(dg_mesh *mesh, int enable);
+
 /* Per-launch timing of the fused stage kernel.  With timing enabled,
  * dg_step and dg_run bracket every stage-kernel launch with a pair of HIP
  * events on the caller's stream (no synchronisation).  dg_kernel_time
@@ -173,6 +180,52 @@ int dg_viscosity(dg_mesh *mesh, const void *U, double *eps, void *stream);
  * dominant kernel's average duration measured inside the timed region. */
 int dg_set_kernel_timing(dg_mesh *mesh, int enable);
 int dg_kernel_time(dg_mesh *mesh, void *stream, double *stage_ms_total, long *stage_launches);
+
+/* Device bytes a handle holds (geometry, operators, scratch) plus one state
+ * array and its work buffer: the unit of HBM-footprint admission. */
+int dg_mesh_footprint(const dg_mesh *mesh, size_t *bytes);
+
+/* Upper estimate of dg_mesh_footprint for a mesh not yet set up, so that a
+ * server can decide admission before allocating anything. */
+int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *bytes);
+
+/* ---- Batching (continuous batching of independent solves) ----------------
+ * A batch holds up to max_slots independent solves (each a dg_mesh with its
+ * own state U and work buffer, all on one device) whose summed footprints
+ * stay within hbm_budget_bytes.  dg_batch_advance moves every active slot
+ * forward in lockstep: for each order P one launch per RK stage covers the
+ * tiles of all FP32 (non-viscous) slots of that order, each with its own
+ * CFL time step computed on the device; other slots are stepped one by one
+ * in the same stream.  Two steps are captured in a hipGraph and replayed
+ * while the membership does not change.  The result of every slot is
+ * bit-identical to running it alone with dg_run.  Slots join (admit) and
+ * leave (release) between calls, so solves that arrive while others are
+ * running start at the next call. */
+typedef struct dg_batch dg_batch;
+
+int dg_batch_create(size_t hbm_budget_bytes, int max_slots, dg_batch **out);
+int dg_batch_destroy(dg_batch *batch);
+
+/* Admit a solve of nsteps CFL steps.  DG_EBUSY if no slot is free or the
+ * footprint does not fit the budget (the caller keeps it queued).  Resets
+ * the handle's time and statistics.  Enqueues on stream. */
+int dg_batch_admit(dg_batch *batch, dg_mesh *mesh, void *U, void *work, int nsteps, void *stream,
+                   int *slot);
+
+/* Advance all active slots by min(max_steps, fewest remaining steps) steps;
+ * *steps_run receives that number.  Enqueues only. */
+int dg_batch_advance(dg_batch *batch, int max_steps, void *stream, int *steps_run);
+
+/* Synchronise the stream and list slots that have finished all their steps
+ * and are not yet released (up to max_done ids; *ndone = how many). */
+int dg_batch_poll(dg_batch *batch, void *stream, int *done_slots, int max_done, int *ndone);
+
+/* Steps done, simulated time, dt range and status of a slot (synchronises). */
+int dg_batch_slot_stats(dg_batch *batch, int slot, void *stream, dg_run_stats *stats);
+
+/* Free a slot and its share of the budget; the handle and buffers stay the
+ * caller's. */
+int dg_batch_release(dg_batch *batch, int slot);
 
 /* Device flag of the last dg_step/dg_run: 1 if a non-finite state,
  * rho <= 0 or p <= 0 was seen.  Synchronises the stream. */

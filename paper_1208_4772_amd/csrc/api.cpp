@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -52,13 +53,23 @@ struct dg_mesh {
             return fail(DG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
         }
         allocs.push_back(q);
+        owned_bytes += count * sizeof(T);
         *p = static_cast<T *>(q);
         return DG_OK;
     }
+    size_t owned_bytes = 0;
     ~dg_mesh() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
+    // hipGraph of two fused steps (parity 0 then 1), replayed by dg_run
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    void *graph_U = nullptr, *graph_work = nullptr;
+
     // per-launch stage-kernel timing (event pairs, reused across calls)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -298,16 +309,8 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
             (rc = m->alloc(&flags_d, size_t(K))) || (rc = m->alloc(&geoA_d, size_t(K) * 16)) ||
             (rc = m->alloc(&opsA_d, nA)))
             return cleanup(rc);
-        std::vector<int> conn4(size_t(K) * 4);
-        for (long k = 0; k < K; ++k) {
-            conn4[k * 4 + 0] = nbr[k * 3 + 0];
-            conn4[k * 4 + 1] = nbr[k * 3 + 1];
-            conn4[k * 4 + 2] = nbr[k * 3 + 2];
-            conn4[k * 4 + 3] = finfo[k];
-        }
         std::vector<float> opsA(nA);
         mfma_fill_opsA(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsA.data());
-        SETUP_TRY(hipMemcpyAsync(conn4_d, conn4.data(), sizeof(int) * conn4.size(), hipMemcpyHostToDevice, st));
         SETUP_TRY(hipMemcpyAsync(opsA_d, opsA.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
         SETUP_TRY(launch_affine_flags(dm, flags_d, st));
         std::vector<int> flags(K), cidx(K);
@@ -315,6 +318,14 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         SETUP_TRY(hipStreamSynchronize(st));
         int Kc = 0;
         for (long k = 0; k < K; ++k) cidx[k] = flags[k] ? -1 : Kc++;
+        std::vector<int> conn4(size_t(K) * 4);
+        for (long k = 0; k < K; ++k) {
+            conn4[k * 4 + 0] = nbr[k * 3 + 0];
+            conn4[k * 4 + 1] = nbr[k * 3 + 1];
+            conn4[k * 4 + 2] = nbr[k * 3 + 2];
+            conn4[k * 4 + 3] = finfo[k] | (cidx[k] >= 0 ? mfma_curved_bit() : 0);
+        }
+        SETUP_TRY(hipMemcpyAsync(conn4_d, conn4.data(), sizeof(int) * conn4.size(), hipMemcpyHostToDevice, st));
         float *geoC_d;
         if ((rc = m->alloc(&geoC_d, size_t(Kc) * (4 * Np + 9 * Nfp)))) return cleanup(rc);
         SETUP_TRY(hipMemcpyAsync(cidx_d, cidx.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
@@ -325,6 +336,17 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         dm.geoC = geoC_d;
         dm.opsA = opsA_d;
         dm.Kc = Kc;
+        unsigned long long *vmax_d;
+        if ((rc = m->alloc(&vmax_d, 2))) return cleanup(rc);
+        dm.vmax = vmax_d;
+        int dev = 0, ncu = 0;
+        SETUP_TRY(hipGetDevice(&dev));
+        SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        dm.ncu = ncu > 0 ? ncu : 256;
+        if (const char *e = std::getenv("DG_BLOCKS_PER_CU")) {
+            const int b = std::atoi(e);
+            if (b >= 1 && b <= 16) dm.blocks_per_cu = b;
+        }
         SETUP_TRY(hipStreamSynchronize(st));
     }
     *out = m;
@@ -392,7 +414,7 @@ int dg_rhs(dg_mesh *m, const void *U, void *rhs, double t, void *stream) {
 // One step: dt reduction on the device, then five stages ping-ponging
 // U -> A -> B -> A -> B -> U so that no stage writes the buffer whose face
 // traces other workgroups are still reading.
-static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st) {
+static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st, int fused_parity = -1) {
     char *w = static_cast<char *>(work);
     void *R = w + m->off_R();
     void *A = w + m->off_A();
@@ -401,6 +423,27 @@ static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st)
     void *eps = m->dm.av ? w + m->off_eps() : nullptr;
     void *in[5] = {U, A, B, A, B};
     void *out[5] = {A, B, A, B, U};
+    if (fused_parity >= 0) {
+        // matrix-core path: dt comes from the CFL bound the previous step's
+        // last stage left in vmax[parity]; this step's last stage fills the other slot
+        for (int s = 0; s < 5; ++s) {
+            MfmaStep ms;
+            ms.dt_fixed = dt;
+            if (s == 0) {
+                ms.cfl_mode = 1;
+                ms.vmax_in = m->dm.vmax + fused_parity;
+                ms.vmax_out = m->dm.vmax + (1 - fused_parity);
+            }
+            if (s == 4) {
+                ms.cfl_accum = 1;
+                ms.vmax_out = m->dm.vmax + (1 - fused_parity);
+            }
+            HIP_TRY(m->time_begin(st));
+            HIP_TRY(launch_stage_mfma(m->dm, in[s], out[s], R, nullptr, s, ms, st));
+            HIP_TRY(m->time_end(st));
+        }
+        return DG_OK;
+    }
     if (m->dm.av) {
         if (int rc = av_prepare(m, U, w, st)) return rc;
     }
@@ -413,6 +456,41 @@ static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st)
         HIP_TRY(launch_stage(m->dm, in[s], out[s], R, nullptr, s, eps, Q, st));
         HIP_TRY(m->time_end(st));
     }
+    return DG_OK;
+}
+
+// Capture two fused steps (parities 0 and 1) of this U/work pair into a
+// graph on a private stream; replays then run on the caller's stream.  The
+// kernels read dt and the CFL bound from device memory, so the graph stays
+// valid from step to step; it is rebuilt when the buffers change.
+static int ensure_step_graph(dg_mesh *m, void *U, void *work) {
+    if (m->graph_exec && m->graph_U == U && m->graph_work == work) return DG_OK;
+    if (m->graph_exec) {
+        HIP_TRY(hipGraphExecDestroy(m->graph_exec));
+        m->graph_exec = nullptr;
+    }
+    if (!m->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed));
+    int rc0 = step_impl(m, U, work, 0.0, m->cap_stream, 0);
+    int rc1 = rc0 ? rc0 : step_impl(m, U, work, 0.0, m->cap_stream, 1);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(m->cap_stream, &g);
+    if (rc1) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc1;
+    }
+    if (ec != hipSuccess) return fail(DG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipError_t ei = hipGraphInstantiate(&m->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(DG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    m->graph_U = U;
+    m->graph_work = work;
+    return DG_OK;
+}
+
+int dg_set_graphs(dg_mesh *m, int enable) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    m->graphs = enable != 0;
     return DG_OK;
 }
 
@@ -435,8 +513,15 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
     HIP_TRY(launch_reset_scalars(m->dm, st));
     HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
     HIP_TRY(hipEventRecord(e0, st));
-    for (int n = 0; n < nsteps; ++n) {
-        if (int rc = step_impl(m, U, work, 0.0, st)) {
+    const bool fused = m->dm.fp32 && !m->dm.av;
+    if (fused && nsteps > 0) HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    int done = 0;
+    if (fused && m->graphs && !m->timing && nsteps >= 2) {
+        if (int rc = ensure_step_graph(m, U, work)) return rc;
+        for (; done + 2 <= nsteps; done += 2) HIP_TRY(hipGraphLaunch(m->graph_exec, st));
+    }
+    for (int n = done; n < nsteps; ++n) {
+        if (int rc = step_impl(m, U, work, 0.0, st, fused ? (n & 1) : -1)) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             return rc;
@@ -557,6 +642,345 @@ int dg_status(dg_mesh *m, void *stream, int *device_flag) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(device_flag, m->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// footprints and batching
+// ---------------------------------------------------------------------------
+
+int dg_mesh_footprint(const dg_mesh *m, size_t *bytes) {
+    if (!m || !bytes) return fail(DG_EINVAL, "null argument");
+    *bytes = m->owned_bytes + m->state_bytes() + m->work_bytes();
+    return DG_OK;
+}
+
+int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *bytes) {
+    if (!bytes || K < 1 || P < 1 || P > 5) return fail(DG_EINVAL, "bad arguments");
+    const size_t Np = size_t(n_nodes(P)), Nfp = size_t(P + 1), k = size_t(K);
+    const size_t s = precision == DG_FP32 ? 4 : 8;
+    size_t b = k * (3 + 1) * 4;                                   // nbr, finfo
+    b += k * Np * 2 * 8;                                          // node coordinates
+    b += k * (4 * Np + 9 * Nfp + Np + 1) * 8;                     // FP64 geometry, mass weights, eps_max
+    if (precision == DG_FP32)
+        b += k * (4 * Np + 9 * Nfp + 1) * 4 + k * (4 + 1 + 1) * 4 + k * 16 * 4  // FP32 copies, conn, flags
+             + k * (4 * Np + 9 * Nfp) * 4;                        // curved records (upper bound)
+    const size_t state = k * 4 * Np * s;
+    size_t work = 3 * align256(state);
+    if (av_enable) work += align256(2 * state) + align256(k * s);
+    *bytes = b + state + work + (1u << 20);                       // operators, scalars, scratch
+    return DG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Slot {
+    bool used = false, finished = false;
+    dg_mesh *mesh = nullptr;
+    void *U = nullptr, *work = nullptr;
+    int total = 0, remaining = 0, parity = 0;
+    size_t footprint = 0;
+};
+
+// Device tables of one order P: argument records [parity][stage][job] and
+// the work list of (job, tile) items.
+struct Group {
+    int P = 0;
+    std::vector<int> slots;
+    void *jobs = nullptr;
+    size_t jobs_cap = 0;
+    void *items = nullptr;
+    size_t items_cap = 0;
+    int nitems = 0;
+};
+
+}  // namespace
+
+struct dg_batch {
+    size_t budget = 0, used = 0;
+    std::vector<Slot> slots;
+    std::vector<Group> groups;
+    std::vector<int> singles;      // slots stepped one by one (FP64 or viscous handles)
+    bool dirty = true;
+    long epoch_steps = 0;          // steps since the tables were last built
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    ~dg_batch() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (Group &g : groups) {
+            if (g.jobs) (void)hipFree(g.jobs);
+            if (g.items) (void)hipFree(g.items);
+        }
+    }
+};
+
+namespace {
+
+bool batched_path(const dg_mesh *m) { return m->dm.fp32 && !m->dm.av; }
+
+// Rebuild the per-order tables for the active, unfinished slots.
+int rebuild(dg_batch *b, hipStream_t st) {
+    std::vector<Group> old;
+    old.swap(b->groups);
+    b->singles.clear();
+    for (int P = 1; P <= 5; ++P) {
+        Group g;
+        g.P = P;
+        for (size_t i = 0; i < b->slots.size(); ++i) {
+            const Slot &s = b->slots[i];
+            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == P) g.slots.push_back(int(i));
+        }
+        if (!g.slots.empty()) b->groups.push_back(std::move(g));
+    }
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const Slot &s = b->slots[i];
+        if (s.used && !s.finished && !batched_path(s.mesh)) b->singles.push_back(int(i));
+    }
+    // reuse old allocations where they are large enough
+    for (Group &g : b->groups) {
+        for (Group &o : old)
+            if (o.P == g.P) {
+                g.jobs = o.jobs;
+                g.jobs_cap = o.jobs_cap;
+                g.items = o.items;
+                g.items_cap = o.items_cap;
+                o.jobs = o.items = nullptr;
+            }
+        const size_t nj = g.slots.size();
+        const size_t rec = mfma_args_bytes();
+        std::vector<char> jobs(2 * 5 * nj * rec);
+        std::vector<int> items;
+        for (size_t j = 0; j < nj; ++j) {
+            Slot &s = b->slots[g.slots[j]];
+            dg_mesh *m = s.mesh;
+            char *w = static_cast<char *>(s.work);
+            void *R = w + m->off_R(), *A = w + m->off_A(), *B = w + m->off_B();
+            void *in[5] = {s.U, A, B, A, B};
+            void *out[5] = {A, B, A, B, s.U};
+            for (int ps = 0; ps < 2; ++ps) {
+                const int par = (s.parity + ps) & 1;
+                for (int st5 = 0; st5 < 5; ++st5) {
+                    MfmaStep ms;
+                    if (st5 == 0) {
+                        ms.cfl_mode = 1;
+                        ms.vmax_in = m->dm.vmax + par;
+                        ms.vmax_out = m->dm.vmax + (1 - par);
+                    }
+                    if (st5 == 4) {
+                        ms.cfl_accum = 1;
+                        ms.vmax_out = m->dm.vmax + (1 - par);
+                    }
+                    mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms,
+                                   jobs.data() + ((ps * 5 + st5) * nj + j) * rec);
+                }
+            }
+            const int nt = mfma_tiles(m->dm);
+            for (int tt = 0; tt < nt; ++tt) {
+                items.push_back(int(j));
+                items.push_back(tt);
+            }
+        }
+        g.nitems = int(items.size() / 2);
+        auto grow = [&](void **p, size_t *cap, size_t need) -> int {
+            if (*cap >= need) return DG_OK;
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+            *cap = 0;
+            if (hipMalloc(p, need) != hipSuccess) return fail(DG_ENOMEM, "batch table allocation failed");
+            *cap = need;
+            return DG_OK;
+        };
+        if (int rc = grow(&g.jobs, &g.jobs_cap, jobs.size())) return rc;
+        if (int rc = grow(&g.items, &g.items_cap, items.size() * sizeof(int))) return rc;
+        HIP_TRY(hipMemcpyAsync(g.jobs, jobs.data(), jobs.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    for (Group &o : old) {
+        if (o.jobs) (void)hipFree(o.jobs);
+        if (o.items) (void)hipFree(o.items);
+    }
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->epoch_steps = 0;
+    b->dirty = false;
+    return DG_OK;
+}
+
+// One lockstep step of every active slot; ps = parity of the epoch step.
+int batch_step(dg_batch *b, int ps, hipStream_t st) {
+    const size_t rec = mfma_args_bytes();
+    for (int s5 = 0; s5 < 5; ++s5)
+        for (const Group &g : b->groups) {
+            const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * g.slots.size() * rec;
+            HIP_TRY(launch_stage_mfma_batch(g.P, jobs, g.items, g.nitems, st));
+        }
+    for (int i : b->singles) {
+        Slot &s = b->slots[i];
+        if (int rc = step_impl(s.mesh, s.U, s.work, 0.0, st)) return rc;
+    }
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_create(size_t hbm_budget_bytes, int max_slots, dg_batch **out) {
+    if (!out) return fail(DG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1) return fail(DG_EINVAL, "max_slots must be >= 1");
+    dg_batch *b = new dg_batch();
+    b->budget = hbm_budget_bytes;
+    b->slots.resize(max_slots);
+    *out = b;
+    return DG_OK;
+}
+
+int dg_batch_destroy(dg_batch *b) {
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    (void)hipDeviceSynchronize();
+    delete b;
+    return DG_OK;
+}
+
+int dg_batch_admit(dg_batch *b, dg_mesh *m, void *U, void *work, int nsteps, void *stream, int *slot) {
+    if (!b || !m || !U || !work || !slot) return fail(DG_EINVAL, "null argument");
+    if (nsteps < 1) return fail(DG_EINVAL, "nsteps must be >= 1");
+    *slot = -1;
+    size_t fp = 0;
+    dg_mesh_footprint(m, &fp);
+    if (b->used + fp > b->budget)
+        return fail(DG_EBUSY, "HBM budget: " + std::to_string(b->used) + " + " + std::to_string(fp) +
+                                  " bytes exceeds " + std::to_string(b->budget));
+    int free_slot = -1;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (!b->slots[i].used) {
+            free_slot = int(i);
+            break;
+        }
+    if (free_slot < 0) return fail(DG_EBUSY, "no free slot");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_reset_scalars(m->dm, st));
+    HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
+    if (batched_path(m)) HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    Slot &s = b->slots[free_slot];
+    s = Slot();
+    s.used = true;
+    s.mesh = m;
+    s.U = U;
+    s.work = work;
+    s.total = s.remaining = nsteps;
+    s.parity = 0;
+    s.footprint = fp;
+    b->used += fp;
+    b->dirty = true;
+    *slot = free_slot;
+    return DG_OK;
+}
+
+int dg_batch_advance(dg_batch *b, int max_steps, void *stream, int *steps_run) {
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    if (steps_run) *steps_run = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int n = max_steps;
+    bool any = false;
+    for (const Slot &s : b->slots)
+        if (s.used && !s.finished) {
+            any = true;
+            n = s.remaining < n ? s.remaining : n;
+        }
+    if (!any || n <= 0) return DG_OK;
+    if (b->dirty)
+        if (int rc = rebuild(b, st)) return rc;
+    int done = 0;
+    // an odd epoch position first takes one eager step
+    if ((b->epoch_steps & 1) && done < n) {
+        if (int rc = batch_step(b, 1, st)) return rc;
+        ++done;
+        ++b->epoch_steps;
+    }
+    if (n - done >= 2) {
+        if (!b->graph) {
+            if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+            int rc0 = batch_step(b, 0, b->cap_stream);
+            int rc1 = rc0 ? rc0 : batch_step(b, 1, b->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
+            if (rc1) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc1;
+            }
+            if (ec != hipSuccess) return fail(DG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return fail(DG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        for (; done + 2 <= n; done += 2) {
+            HIP_TRY(hipGraphLaunch(b->graph, st));
+            b->epoch_steps += 2;
+        }
+    }
+    for (; done < n; ++done) {
+        if (int rc = batch_step(b, int(b->epoch_steps & 1), st)) return rc;
+        ++b->epoch_steps;
+    }
+    for (Slot &s : b->slots)
+        if (s.used && !s.finished) {
+            s.remaining -= n;
+            s.parity = (s.parity + n) & 1;
+            if (s.remaining == 0) {
+                s.finished = true;
+                b->dirty = true;
+            }
+        }
+    if (steps_run) *steps_run = n;
+    return DG_OK;
+}
+
+int dg_batch_poll(dg_batch *b, void *stream, int *done_slots, int max_done, int *ndone) {
+    if (!b || !ndone) return fail(DG_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    int n = 0;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i].used && b->slots[i].finished) {
+            if (done_slots && n < max_done) done_slots[n] = int(i);
+            ++n;
+        }
+    *ndone = n;
+    return DG_OK;
+}
+
+int dg_batch_slot_stats(dg_batch *b, int slot, void *stream, dg_run_stats *stats) {
+    if (!b || !stats || slot < 0 || slot >= int(b->slots.size()) || !b->slots[slot].used)
+        return fail(DG_EINVAL, "bad slot");
+    const Slot &s = b->slots[slot];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double scal[S_NSCAL];
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(scal, s.mesh->dm.scal, sizeof(scal), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&flag, s.mesh->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->steps = s.total - s.remaining;
+    stats->status = flag ? DG_ENONFINITE : DG_OK;
+    stats->t = scal[S_T];
+    stats->dt_min = stats->steps ? scal[S_DTMIN] : 0.0;
+    stats->dt_max = scal[S_DTMAX];
+    return DG_OK;
+}
+
+int dg_batch_release(dg_batch *b, int slot) {
+    if (!b || slot < 0 || slot >= int(b->slots.size()) || !b->slots[slot].used)
+        return fail(DG_EINVAL, "bad slot");
+    b->used -= b->slots[slot].footprint;
+    b->slots[slot] = Slot();
+    b->dirty = true;
     return DG_OK;
 }
 

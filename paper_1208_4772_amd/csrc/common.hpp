@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 namespace dg {
 
 constexpr int kFields = 4;  // rho, rho u, rho v, E
@@ -43,29 +45,69 @@ __host__ __device__ inline int face_bc(int info, int f) { return (info >> (4 * f
 
 enum { BC_INTERIOR = 0, BC_WALL = 1, BC_FARFIELD = 2 };
 
+// Reciprocal and square root: exact (IEEE) in FP64; the single-instruction
+// hardware versions (about 1 ulp) in FP32, whose results are checked against
+// the FP64 oracle to the FP32 tolerance.
+__device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fpow(double x, double y) { return pow(x, y); }
+__device__ inline float fpow(float x, float y) { return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)); }
+
+// p = (gamma-1)(E - (m_x^2 + m_y^2)/(2 rho)), given ir = 1/rho
+template <typename T>
+__device__ inline T pressure_ir(T g, const T u[kFields], T ir) {
+    return (g - T(1)) * (u[3] - T(0.5) * (u[1] * u[1] + u[2] * u[2]) * ir);
+}
+
 template <typename T>
 __device__ inline T pressure(T g, const T u[kFields]) {
-    return (g - T(1)) * (u[3] - T(0.5) * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    return pressure_ir(g, u, rcp(u[0]));
+}
+
+// Far-field state in primitive form, prepared once on the host.
+template <typename T>
+struct FarField {
+    T q[kFields];     // conserved (rho, rho u, rho v, E)
+    T rho, u, v, c;   // primitives and sound speed
+    T s;              // entropy p / rho^gamma
+    T inv_gm1;        // 1 / (gamma - 1)
+};
+
+template <typename T>
+FarField<T> make_farfield(double g, const double q[kFields]) {
+    const double rho = q[0], u = q[1] / rho, v = q[2] / rho;
+    const double p = (g - 1.0) * (q[3] - 0.5 * rho * (u * u + v * v));
+    FarField<T> f;
+    for (int c = 0; c < kFields; ++c) f.q[c] = T(q[c]);
+    f.rho = T(rho);
+    f.u = T(u);
+    f.v = T(v);
+    f.c = T(std::sqrt(g * p / rho));
+    f.s = T(p / std::pow(rho, g));
+    f.inv_gm1 = T(1.0 / (g - 1.0));
+    return f;
 }
 
 // Normal flux n.F(u) and the wave speed |v.n| + c.
 template <typename T>
 __device__ inline void normal_flux(T g, const T u[kFields], T nx, T ny, T fn[kFields], T &lam) {
-    T ir = T(1) / u[0];
+    T ir = rcp(u[0]);
     T vx = u[1] * ir, vy = u[2] * ir;
-    T p = pressure(g, u);
+    T p = pressure_ir(g, u, ir);
     T vn = vx * nx + vy * ny;
     fn[0] = u[0] * vn;
     fn[1] = u[1] * vn + p * nx;
     fn[2] = u[2] * vn + p * ny;
     fn[3] = (u[3] + p) * vn;
-    lam = fabs(vn) + sqrt(g * p * ir);
+    lam = fabs(vn) + fsqrt(g * p * ir);
 }
 
 // Boundary ghost state: slip-wall mirror or characteristic far field.
 template <typename T>
 __device__ inline void ghost_state(T g, int code, const T um[kFields], T nx, T ny,
-                                   const T qinf[kFields], T up[kFields]) {
+                                   const FarField<T> &ff, T up[kFields]) {
     if (code == BC_WALL) {
         T mn = um[1] * nx + um[2] * ny;
         up[0] = um[0];
@@ -74,14 +116,12 @@ __device__ inline void ghost_state(T g, int code, const T um[kFields], T nx, T n
         up[3] = um[3];
         return;
     }
-    T rhoi = um[0], ui = um[1] / rhoi, vi = um[2] / rhoi;
-    T pi = pressure(g, um), ci = sqrt(g * pi / rhoi);
+    T rhoi = um[0], iri = rcp(rhoi), ui = um[1] * iri, vi = um[2] * iri;
+    T pi = pressure_ir(g, um, iri), ci = fsqrt(g * pi * iri);
     T vni = ui * nx + vi * ny;
-    T rhoo = qinf[0], uo = qinf[1] / rhoo, vo = qinf[2] / rhoo;
-    T po = pressure(g, qinf), co = sqrt(g * po / rhoo);
-    T vno = uo * nx + vo * ny;
+    T vno = ff.u * nx + ff.v * ny;
     if (vni <= -ci) {
-        for (int c = 0; c < kFields; ++c) up[c] = qinf[c];
+        for (int c = 0; c < kFields; ++c) up[c] = ff.q[c];
         return;
     }
     if (vni >= ci) {
@@ -89,27 +129,27 @@ __device__ inline void ghost_state(T g, int code, const T um[kFields], T nx, T n
         return;
     }
     T gm1 = g - T(1);
-    T Rout = vni + T(2) * ci / gm1;
-    T Rin = vno - T(2) * co / gm1;
+    T Rout = vni + T(2) * ci * ff.inv_gm1;
+    T Rin = vno - T(2) * ff.c * ff.inv_gm1;
     T vnb = T(0.5) * (Rout + Rin);
     T cb = T(0.25) * gm1 * (Rout - Rin);
     T sb, utb, vtb;
     if (vnb > T(0)) {
-        sb = pi / pow(rhoi, g);
+        sb = pi * rcp(fpow(rhoi, g));
         utb = ui - vni * nx;
         vtb = vi - vni * ny;
     } else {
-        sb = po / pow(rhoo, g);
-        utb = uo - vno * nx;
-        vtb = vo - vno * ny;
+        sb = ff.s;
+        utb = ff.u - vno * nx;
+        vtb = ff.v - vno * ny;
     }
-    T rhob = pow(cb * cb / (g * sb), T(1) / gm1);
-    T pb = rhob * cb * cb / g;
+    T rhob = fpow(cb * cb * rcp(g * sb), ff.inv_gm1);
+    T pb = rhob * cb * cb * rcp(g);
     T ub = utb + vnb * nx, vb = vtb + vnb * ny;
     up[0] = rhob;
     up[1] = rhob * ub;
     up[2] = rhob * vb;
-    up[3] = pb / gm1 + T(0.5) * rhob * (ub * ub + vb * vb);
+    up[3] = pb * ff.inv_gm1 + T(0.5) * rhob * (ub * ub + vb * vb);
 }
 
 // n.F(u-) - F*(u-, u+) for the local Lax-Friedrichs flux

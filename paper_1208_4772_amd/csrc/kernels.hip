@@ -25,7 +25,7 @@ template <typename T>
 struct StageArgs {
     int K, stage, mode;
     T g, ra, rb;
-    T qinf[4];
+    FarField<T> ff;
     const T *__restrict__ Uin;
     T *__restrict__ Uout;
     T *__restrict__ R;
@@ -75,9 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     if (t.act) {
 #pragma unroll
         for (int c = 0; c < kFields; ++c) u[c] = a.Uin[(k * kFields + c) * Np + i];
-        T ir = T(1) / u[0];
+        T ir = rcp(u[0]);
         T vx = u[1] * ir, vy = u[2] * ir;
-        T p = pressure(a.g, u);
+        T p = pressure_ir(a.g, u, ir);
         T F[kFields] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
         T G[kFields] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
         if (AV) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < kFields; ++c) up[c] = a.Uin[(kn * kFields + c) * Np + vp];
             } else {
-                ghost_state(a.g, code, um, nx, ny, a.qinf, up);
+                ghost_state(a.g, code, um, nx, ny, a.ff, up);
             }
             lf_jump(a.g, um, up, nx, ny, d);
             if (AV) {
@@ -186,7 +186,7 @@ template <typename T>
 struct AvArgs {
     int K, P;
     T g;
-    T qinf[4];
+    FarField<T> ff;
     double s0, kappa;
     const T *__restrict__ U;
     const T *__restrict__ eps_in;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < kFields; ++c) up[c] = a.U[(kn * kFields + c) * Np + vp];
             } else {
-                ghost_state(a.g, code, um, nx, ny, a.qinf, up);
+                ghost_state(a.g, code, um, nx, ny, a.ff, up);
             }
 #pragma unroll
             for (int c = 0; c < kFields; ++c) {
@@ -566,6 +566,15 @@ __global__ __launch_bounds__(kBlock) void k_cfl_finish(int n, const double *__re
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_cfl_finish_vmax(int n, const double *__restrict__ partial,
+                                                            unsigned long long *__restrict__ slot) {
+    __shared__ double sh[kBlock];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < n; b += kBlock) v = v > partial[b] ? v : partial[b];
+    const double vmax = block_reduce(v, sh, MaxOp());
+    if (threadIdx.x == 0) *slot = (unsigned long long)__double_as_longlong(vmax);
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_totals(int K, const T *__restrict__ U,
                                                    const double *__restrict__ wmass,
@@ -691,7 +700,7 @@ hipError_t stage_t(const DevMesh &m, const void *Uin, void *Uout, void *R, void 
     a.g = T(m.gamma);
     a.ra = T(rk_a(stage));
     a.rb = T(rk_b(stage));
-    for (int c = 0; c < 4; ++c) a.qinf[c] = T(m.qinf[c]);
+    a.ff = make_farfield<T>(m.gamma, m.qinf);
     a.Uin = static_cast<const T *>(Uin);
     a.Uout = static_cast<T *>(Uout);
     a.R = static_cast<T *>(R);
@@ -720,7 +729,7 @@ AvArgs<T> av_args(const DevMesh &m) {
     a.K = m.K;
     a.P = m.P;
     a.g = T(m.gamma);
-    for (int c = 0; c < 4; ++c) a.qinf[c] = T(m.qinf[c]);
+    a.ff = make_farfield<T>(m.gamma, m.qinf);
     a.s0 = m.av_s0;
     a.kappa = m.av_kappa;
     a.nbr = m.nbr;
@@ -785,7 +794,7 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) 
 
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                         const void *eps, const void *Q, hipStream_t st) {
-    if (m.fp32 && !m.av) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, st);
+    if (m.fp32 && !m.av) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st);
     return m.fp32 ? stage_t<float>(m, Uin, Uout, R, rhs, stage, eps, Q, st)
                   : stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }
@@ -841,6 +850,24 @@ static hipError_t cfl_t(const DevMesh &m, const void *U, const void *eps, double
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(kBlock), 0, st, nblocks_rt(m.K, m.P), m.partial,
                        m.cfl, dt_fixed, m.scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st) {
+    hipError_t e = with_order(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        if (m.fp32)
+            hipLaunchKernelGGL((k_cfl<float, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                               m.gamma, static_cast<const float *>(U), (const float *)nullptr, m.fgeo64,
+                               m.partial, m.flag);
+        else
+            hipLaunchKernelGGL((k_cfl<double, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, m.K,
+                               m.gamma, static_cast<const double *>(U), (const double *)nullptr, m.fgeo64,
+                               m.partial, m.flag);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cfl_finish_vmax, dim3(1), dim3(kBlock), 0, st, nblocks_rt(m.K, m.P), m.partial, slot);
     return hipGetLastError();
 }
 

@@ -42,6 +42,9 @@ struct DevMesh {
     const float *geoC = nullptr;    // [Kc][4 Np + 9 Nfp] curved geometry
     const float *opsA = nullptr;    // MFMA A operand table
     int Kc = 0;
+    int ncu = 256;                  // compute units of the device
+    int blocks_per_cu = 4;          // persistent blocks per CU (matrix-core kernel)
+    unsigned long long *vmax = nullptr;   // [2] CFL-bound slots (FP64 bit patterns)
     // device scalars and reduction scratch
     double *scal = nullptr;   // [S_NSCAL]
     int *flag = nullptr;      // non-finite / non-positive state flag
@@ -74,9 +77,27 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st);
 // eps: [K] viscosities and Q: [K][2][4][Np] gradients (AV only).
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
                         int stage, const void *eps, const void *Q, hipStream_t st);
+// Time-step handling of one matrix-core stage launch.
+struct MfmaStep {
+    int cfl_mode = 0;      // 1: first stage computes dt from *vmax_in (and books it)
+    int cfl_accum = 0;     // 1: last stage reduces the new state's CFL bound into *vmax_out
+    double dt_fixed = 0.0; // > 0 overrides the CFL step when cfl_mode = 1
+    const unsigned long long *vmax_in = nullptr;
+    unsigned long long *vmax_out = nullptr;
+};
 // FP32 matrix-core stage kernel (no artificial viscosity)
 hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
-                             int stage, hipStream_t st);
+                             int stage, const MfmaStep &step, hipStream_t st);
+int mfma_curved_bit();
+// batched meshes: per-(mesh, stage) argument records in device memory and a
+// work list of (record, tile) items, all meshes of order P
+size_t mfma_args_bytes();
+void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
+                    void *out);
+int mfma_tiles(const DevMesh &m);
+hipError_t launch_stage_mfma_batch(int P, const void *jobs, const void *items, int nitems, hipStream_t st);
+// CFL bound of state U (FP64) into *slot as a bit pattern; raises *flag on bad states
+hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st);
 size_t mfma_opsA_floats(int P);
 void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out);
 int mfma_elements_per_block(int P);

@@ -6,20 +6,29 @@
 //   F' = r_x F + r_y G,  G' = s_x F + s_y G,
 // and the whole right-hand side of a field becomes one product
 //   rhs = [-Dr  -Ds  LIFT] (Np x (2Np + 3Nfp))  .  [F'; G'; Fscale (n.F - F*)].
-// The kernel forms that product for blocks of 4 elements x 4 fields = 16
-// columns on the MFMA unit (A operand resident in VGPRs for the whole
-// kernel, B operand staged in LDS).  A curved element keeps its per-node
-// metrics: its F', G' rows are zeroed (the product then yields only the LIFT
-// term) and its volume term is formed separately with per-node metrics on
-// the vector ALUs.
+// The kernel forms that product for groups of 4 elements x 4 fields = 16
+// columns on the MFMA unit (A operand staged per block in LDS, B operand
+// built in LDS).  A curved element keeps its per-node metrics: its F', G'
+// rows are zeroed (the product then yields only the LIFT term) and its
+// volume term is formed separately with per-node metrics on the VALUs.
 //
 // Memory: the element tile's state, the Runge-Kutta register and the
 // outputs move as one coalesced 16-byte access per lane; per-element
 // geometry (13 floats for an affine element) and connectivity (16 bytes)
-// likewise; the only scattered reads are the neighbours' face traces.
-// Blocks are remapped so that each XCD sweeps a contiguous range of tiles,
-// which keeps recently loaded neighbours in that XCD's L2.
+// likewise; the only scattered reads are the neighbours' face traces
+// (neighbours inside the tile come from LDS).  Blocks are remapped so that
+// each XCD sweeps a contiguous range of tiles, which keeps recently loaded
+// neighbours in that XCD's L2.  Registers and LDS are kept low (A operand
+// in LDS, the result staged in the B operand's own space) so that five to
+// six blocks share a CU and hide each other's memory latency.
+//
+// Time step: in a fused run the last stage also reduces the CFL bound of
+// the new state (FP64 arithmetic) into a device slot, and the next step's
+// first stage turns it into dt, so a step needs no separate reduction
+// launches.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -30,6 +39,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
+constexpr int kCurvedBit = 1 << 12;   // in the packed face-info word
 
 template <int P>
 struct MShape {
@@ -42,15 +52,19 @@ struct MShape {
     static constexpr int MT = (Np + 15) / 16;   // 16-row output tiles
     static constexpr int EW = 64 / Np;          // elements per wavefront (pointwise phase)
     static constexpr int EB = 4 * EW;           // elements per block
-    static constexpr int NT = EB / 4;           // 16-column tiles per block
-    static constexpr int TILE_FLOATS = EB * 4 * Np;   // state floats per block (<= 1024)
-    static_assert(TILE_FLOATS <= 4 * kBlock, "one float4 per thread covers the tile");
+    static constexpr int NT = EB / 4;           // 16-column groups per block
+    static constexpr int TF = EB * 4 * Np;      // state floats per block (<= 1024)
+    static_assert(TF <= 4 * kBlock, "one float4 per thread covers the tile");
+    static_assert(16 * Np <= 16 * KP, "a column group's result fits in its B block");
 };
 
 struct MfmaArgs {
     int K, stage, mode, nblocks, chunk;
+    int cfl_mode;    // 1: this (first) stage turns *vmax_in into dt
+    int cfl_accum;   // 1: this (last) stage reduces the new state's CFL bound into *vmax_out
     float g, ra, rb;
-    float qinf[4];
+    FarField<float> ff;
+    double gamma, cfl, dt_fixed;
     const float *__restrict__ Uin;
     float *__restrict__ Uout;
     float *__restrict__ R;
@@ -61,59 +75,72 @@ struct MfmaArgs {
     const float *__restrict__ geoC;    // [Kc][4 Np + 9 Nfp]
     const float *__restrict__ opsA;    // [MT][KS][64] A operand in lane order
     const float *__restrict__ ops;     // Dr | Ds (row-major) for curved elements
-    const double *__restrict__ dt;
+    double *__restrict__ scal;
+    const unsigned long long *__restrict__ vmax_in;
+    unsigned long long *__restrict__ vmax_out;
+    int *__restrict__ flag;
 };
 
+// One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
+// arguments (single mesh) or in a device job table (batched meshes); its
+// fields are uniform across the block.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
+__device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     using S = MShape<P>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KP = S::KP, MT = S::MT;
-    constexpr int EW = S::EW, EB = S::EB, NT = S::NT;
-    // XCD-aware tile order: block b runs on XCD b % 8; give each XCD a
-    // contiguous run of tiles.
-    const int tile = (blockIdx.x % 8) * a.chunk + blockIdx.x / 8;
-    if (tile >= a.nblocks) return;
+    constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF;
+
+    // ---- time step of this stage
+    double dtd = 0.0;
+    if (a.cfl_mode) {
+        const double vmax = __longlong_as_double((long long)*a.vmax_in);
+        dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * (1.0 / vmax);
+        if (tile == 0 && threadIdx.x == 0) {
+            a.scal[S_DT] = dtd;
+            a.scal[S_T] += dtd;
+            a.scal[S_DTMIN] = dtd < a.scal[S_DTMIN] ? dtd : a.scal[S_DTMIN];
+            a.scal[S_DTMAX] = dtd > a.scal[S_DTMAX] ? dtd : a.scal[S_DTMAX];
+            a.scal[S_STEPS] += 1.0;
+            *a.vmax_out = 0ull;
+        }
+    } else if (a.mode) {
+        dtd = a.scal[S_DT];
+    }
+
     const long k0 = (long)tile * EB;
     const int nel = (int)min((long)EB, (long)a.K - k0);
 
-    __shared__ float sU[EB * 4 * Np];
-    __shared__ float sR[EB * 4 * Np];
-    __shared__ float sB[NT][KP][16];
+    __shared__ float sU[TF];
+    __shared__ float sB[NT][KP][16];    // B operand; afterwards the result of that column group
+    __shared__ float sA[MT * KS * 64];
     __shared__ float sG[EB][16];
-    __shared__ int sC[EB][4];
-    __shared__ int sCurved[EB];
+    __shared__ int4 sC[EB];
     __shared__ int sAny;
+    __shared__ double sRed[kBlock / 64];
+    __shared__ int sFN[NF3];          // face node ids, face-major, counter-clockwise
+    __shared__ float sPrim[EB][Np][4];  // 1/rho, p, sound speed, unused (pointwise phase)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long base = k0 * 4 * Np;
     const int nflt = nel * 4 * Np;
+    // result (element el, field c, node i) lives in its column group's block
+    auto res = [&](int el, int off) -> float & { return (&sB[el >> 2][0][0])[(el & 3) * 4 * Np + off]; };
 
-    // ---- coalesced tile loads: state, RK register, geometry, connectivity
+    // ---- coalesced tile loads: state, RK register, geometry, connectivity, A
     f32x4 u4 = {0, 0, 0, 0}, r4 = {0, 0, 0, 0};
     const bool flat_ok = 4 * tid < nflt;
     if (flat_ok) {
         u4 = *reinterpret_cast<const f32x4 *>(a.Uin + base + 4 * tid);
         if (a.mode && a.stage > 0) r4 = *reinterpret_cast<const f32x4 *>(a.R + base + 4 * tid);
     }
-    if (tid < 4 * nel) {
-        const float4 gv = a.geoA[k0 * 4 + tid];
-        sG[tid >> 2][(tid & 3) * 4 + 0] = gv.x;
-        sG[tid >> 2][(tid & 3) * 4 + 1] = gv.y;
-        sG[tid >> 2][(tid & 3) * 4 + 2] = gv.z;
-        sG[tid >> 2][(tid & 3) * 4 + 3] = gv.w;
-    }
-    if (tid < nel) {
-        const int4 cv = a.conn[k0 + tid];
-        sC[tid][0] = cv.x;
-        sC[tid][1] = cv.y;
-        sC[tid][2] = cv.z;
-        sC[tid][3] = cv.w;
-        sCurved[tid] = a.cidx[k0 + tid];
-    }
+    if (tid < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid] = a.geoA[k0 * 4 + tid];
+    if (tid < nel) sC[tid] = a.conn[k0 + tid];
+    for (int z = tid; z < MT * KS * 16; z += kBlock)
+        reinterpret_cast<f32x4 *>(sA)[z] = reinterpret_cast<const f32x4 *>(a.opsA)[z];
     if (tid == 0) sAny = 0;
+    if (tid < NF3) sFN[tid] = face_node(P, tid / Nfp, tid % Nfp);
     if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
-    // zero the padded contraction rows of every column tile
     if constexpr (KP > S::KV) {
         constexpr int PADN = (KP - S::KV) * 16;
         for (int z = tid; z < NT * PADN; z += kBlock) {
@@ -121,73 +148,69 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
             sB[t][S::KV + rem / 16][rem % 16] = 0.f;
         }
     }
-    // A operand for the whole kernel
-    float A[MT][KS];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) A[mt][ks] = a.opsA[(mt * KS + ks) * 64 + lane];
     __syncthreads();
 
     // ---- pointwise fluxes (lane = element * Np + node within the wavefront)
-    {
-        const int le = lane / Np, i = lane - le * Np;
-        const int el = wave * EW + le;
-        if (le < EW && el < nel) {
-            float u[4];
+    const int le = lane / Np, in = lane - le * Np;
+    const int eln = wave * EW + le;
+    const bool node_ok = le < EW && eln < nel;
+    bool curved_lane = false;
+    if (node_ok) {
+        float u[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = sU[(el * 4 + c) * Np + i];
-            const float ir = 1.f / u[0];
-            const float vx = u[1] * ir, vy = u[2] * ir;
-            const float p = pressure(a.g, u);
-            const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
-            const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
-            const int t = el >> 2, col = (el & 3) * 4;
-            f32x4 f, gg;
-            if (sCurved[el] < 0) {
-                const float rx = sG[el][0], sx = sG[el][1], ry = sG[el][2], sy = sG[el][3];
+        for (int c = 0; c < 4; ++c) u[c] = sU[(eln * 4 + c) * Np + in];
+        const float ir = rcp(u[0]);
+        const float vx = u[1] * ir, vy = u[2] * ir;
+        const float p = pressure_ir(a.g, u, ir);
+        const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
+        const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
+        *reinterpret_cast<f32x4 *>(&sPrim[eln][in][0]) = f32x4{ir, p, fsqrt(a.g * p * ir), 0.f};
+        const int t = eln >> 2, col = (eln & 3) * 4;
+        f32x4 f, gg;
+        curved_lane = sC[eln].w & kCurvedBit;
+        if (!curved_lane) {
+            const float rx = sG[eln][0], sx = sG[eln][1], ry = sG[eln][2], sy = sG[eln][3];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    f[c] = rx * F[c] + ry * G[c];
-                    gg[c] = sx * F[c] + sy * G[c];
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    f[c] = F[c];
-                    gg[c] = G[c];
-                }
-                sAny = 1;
+            for (int c = 0; c < 4; ++c) {
+                f[c] = rx * F[c] + ry * G[c];
+                gg[c] = sx * F[c] + sy * G[c];
             }
-            *reinterpret_cast<f32x4 *>(&sB[t][i][col]) = f;
-            *reinterpret_cast<f32x4 *>(&sB[t][Np + i][col]) = gg;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                f[c] = F[c];
+                gg[c] = G[c];
+            }
+            sAny = 1;
         }
+        *reinterpret_cast<f32x4 *>(&sB[t][in][col]) = f;
+        *reinterpret_cast<f32x4 *>(&sB[t][Np + in][col]) = gg;
     }
-    // ---- face gather and Lax-Friedrichs flux (task = element * 3Nfp + face node)
+    __syncthreads();
+    // ---- Lax-Friedrichs flux at the face nodes (task = element * 3Nfp + face node)
     for (int task = tid; task < nel * NF3; task += kBlock) {
         const int el = task / NF3, q = task - el * NF3;
         const int f = q / Nfp, j = q - f * Nfp;
-        const int vm = face_node(P, f, j);
+        const int vm = sFN[q];
         float um[4], up[4], d[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) um[c] = sU[(el * 4 + c) * Np + vm];
+        const int4 cv = sC[el];
         float nx, ny, fs;
-        const int cs = sCurved[el];
-        if (cs < 0) {
+        if (!(cv.w & kCurvedBit)) {
             nx = sG[el][4 + 3 * f];
             ny = sG[el][5 + 3 * f];
             fs = sG[el][6 + 3 * f];
         } else {
-            const float *gc = a.geoC + (long)cs * (4 * Np + 9 * Nfp) + 4 * Np;
+            const float *gc = a.geoC + (long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np;
             nx = gc[q];
             ny = gc[NF3 + q];
             fs = gc[2 * NF3 + q];
         }
-        const int info = sC[el][3];
-        const int code = face_bc(info, f);
+        const int code = face_bc(cv.w, f);
         if (code == BC_INTERIOR) {
-            const long kn = sC[el][f];
-            const int vp = face_node(P, face_nbr_face(info, f), Nfp - 1 - j);
+            const long kn = f == 0 ? cv.x : (f == 1 ? cv.y : cv.z);
+            const int vp = sFN[face_nbr_face(cv.w, f) * Nfp + Nfp - 1 - j];
             const long ln = kn - k0;
             if (ln >= 0 && ln < nel) {
 #pragma unroll
@@ -197,28 +220,41 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
                 for (int c = 0; c < 4; ++c) up[c] = a.Uin[(kn * 4 + c) * Np + vp];
             }
         } else {
-            ghost_state(a.g, code, um, nx, ny, a.qinf, up);
+            ghost_state(a.g, code, um, nx, ny, a.ff, up);
         }
-        lf_jump(a.g, um, up, nx, ny, d);
-        f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
+        {
+            // n.F(U-) and its wave speed from the pointwise phase's primitives
+            const f32x4 pm = *reinterpret_cast<const f32x4 *>(&sPrim[el][vm][0]);
+            const float vnm = (um[1] * nx + um[2] * ny) * pm[0];
+            float fm[4] = {um[0] * vnm, um[1] * vnm + pm[1] * nx, um[2] * vnm + pm[1] * ny,
+                           (um[3] + pm[1]) * vnm};
+            const float lm = fabsf(vnm) + pm[2];
+            float fp[4], lp;
+            normal_flux(a.g, up, nx, ny, fp, lp);
+            const float lam = lm > lp ? lm : lp;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
+        }
+        const f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
         *reinterpret_cast<f32x4 *>(&sB[el >> 2][2 * Np + q][(el & 3) * 4]) = jv;
     }
     __syncthreads();
 
-    // ---- curved elements: volume term with per-node metrics (VALU), then
-    // clear their F/G rows so the product contributes only the LIFT term
-    if (sAny) {
-        const int le = lane / Np, i = lane - le * Np;
-        const int el = wave * EW + le;
-        const bool curved = le < EW && el < nel && sCurved[el] >= 0;
-        if (curved) {
-            const float *gc = a.geoC + (long)sCurved[el] * (4 * Np + 9 * Nfp);
-            const float rx = gc[i], sx = gc[Np + i], ry = gc[2 * Np + i], sy = gc[3 * Np + i];
-            const int t = el >> 2, col = (el & 3) * 4;
+    // ---- curved elements: volume term with per-node metrics (VALU), kept
+    // in registers; their F/G rows are then cleared so the product gives
+    // only the LIFT term
+    float vol[4] = {0, 0, 0, 0};
+    const bool any_curved = sAny;
+    if (any_curved) {
+        if (curved_lane) {
+            const float *gc = a.geoC + (long)a.cidx[k0 + eln] * (4 * Np + 9 * Nfp);
+            const float rx = gc[in], sx = gc[Np + in], ry = gc[2 * Np + in], sy = gc[3 * Np + in];
+            const int t = eln >> 2, col = (eln & 3) * 4;
             float drf[4] = {0, 0, 0, 0}, dsf[4] = {0, 0, 0, 0}, drg[4] = {0, 0, 0, 0},
                   dsg[4] = {0, 0, 0, 0};
+#pragma unroll 1
             for (int j = 0; j < Np; ++j) {
-                const float dr = a.ops[i * Np + j], ds = a.ops[Np * Np + i * Np + j];
+                const float dr = a.ops[in * Np + j], ds = a.ops[Np * Np + in * Np + j];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float fv = sB[t][j][col + c], gv = sB[t][Np + j][col + c];
@@ -229,65 +265,150 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
                 }
             }
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                sR[(el * 4 + c) * Np + i] = -(rx * drf[c] + sx * dsf[c] + ry * drg[c] + sy * dsg[c]);
+            for (int c = 0; c < 4; ++c) vol[c] = -(rx * drf[c] + sx * dsf[c] + ry * drg[c] + sy * dsg[c]);
         }
         __syncthreads();
-        if (curved) {
-            const int t = el >> 2, col = (el & 3) * 4;
+        if (curved_lane) {
+            const int t = eln >> 2, col = (eln & 3) * 4;
             const f32x4 z = {0, 0, 0, 0};
-            *reinterpret_cast<f32x4 *>(&sB[t][i][col]) = z;
-            *reinterpret_cast<f32x4 *>(&sB[t][Np + i][col]) = z;
+            *reinterpret_cast<f32x4 *>(&sB[t][in][col]) = z;
+            *reinterpret_cast<f32x4 *>(&sB[t][Np + in][col]) = z;
         }
         __syncthreads();
     }
 
-    // ---- the contraction on the matrix cores: wave w takes column tiles
-    // w, w+4, ...; result row m = node, column n = 4 * element + field
+    // ---- the contraction on the matrix cores: wave w takes column groups
+    // w, w+4, ...; result row = node, column = 4 * element + field.  The
+    // wavefront writes the result over its own (fully consumed) B block.
     for (int t = wave; t < NT; t += 4) {
-        f32x4 acc[MT];
+        // two independent accumulation chains per output tile (even and odd
+        // k-steps) halve the dependent-MFMA latency
+        f32x4 acc[MT], acc2[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0, 0, 0, 0};
+        for (int mt = 0; mt < MT; ++mt) {
+            acc[mt] = f32x4{0, 0, 0, 0};
+            acc2[mt] = f32x4{0, 0, 0, 0};
+        }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const float b = sB[t][4 * ks + (lane >> 4)][lane & 15];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt][ks], b, acc[mt], 0, 0, 0);
+            for (int mt = 0; mt < MT; ++mt) {
+                if (ks & 1)
+                    acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[(mt * KS + ks) * 64 + lane], b,
+                                                                    acc2[mt], 0, 0, 0);
+                else
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[(mt * KS + ks) * 64 + lane], b,
+                                                                   acc[mt], 0, 0, 0);
+            }
         }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] += acc2[mt];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         const int el = t * 4 + ((lane & 15) >> 2), c = lane & 3;
         if (el < nel) {
-            const bool add = sCurved[el] >= 0;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * mt + 4 * (lane >> 4) + r;
-                    if (i < Np) {
-                        float *dst = &sR[(el * 4 + c) * Np + i];
-                        *dst = add ? *dst + acc[mt][r] : acc[mt][r];
-                    }
+                    if (i < Np) res(el, c * Np + i) = acc[mt][r];
                 }
         }
     }
     __syncthreads();
+    if (any_curved) {
+        if (curved_lane) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) res(eln, c * Np + in) += vol[c];
+        }
+        __syncthreads();
+    }
 
     // ---- epilogue: Runge-Kutta update (or the bare rhs), coalesced
+    const int fe = (4 * tid) / (4 * Np), foff = 4 * tid - fe * 4 * Np;
     if (flat_ok) {
-        const f32x4 rh = *reinterpret_cast<const f32x4 *>(&sR[4 * tid]);
+        const f32x4 rh = *reinterpret_cast<const f32x4 *>(&res(fe, foff));
         if (a.mode == 0) {
             *reinterpret_cast<f32x4 *>(a.rhs + base + 4 * tid) = rh;
         } else {
-            const float dt = float(*a.dt);
-            f32x4 rn;
-            if (a.stage == 0)
-                rn = dt * rh;
-            else
-                rn = a.ra * r4 + dt * rh;
+            const float dt = float(dtd);
+            const f32x4 rn = a.stage == 0 ? dt * rh : a.ra * r4 + dt * rh;
+            const f32x4 un = u4 + a.rb * rn;
             *reinterpret_cast<f32x4 *>(a.R + base + 4 * tid) = rn;
-            *reinterpret_cast<f32x4 *>(a.Uout + base + 4 * tid) = u4 + a.rb * rn;
+            *reinterpret_cast<f32x4 *>(a.Uout + base + 4 * tid) = un;
+            if (a.cfl_accum) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = un;
         }
     }
+    if (a.cfl_accum) {
+        // CFL bound and state check of the new state (FP64 arithmetic)
+        __syncthreads();
+        const double g = a.gamma, P1 = P + 1.0;
+        double vmax_blk = 0.0;
+        int bad = 0;
+        if (node_ok) {
+            double u[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[c] = double(sU[(eln * 4 + c) * Np + in]);
+            const double p = (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+            if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+                !isfinite(p))
+                bad = 1;
+        }
+        for (int task = tid; task < nel * NF3; task += kBlock) {
+            const int el = task / NF3, q = task - el * NF3;
+            const int f = q / Nfp, j = q - f * Nfp;
+            const int v = face_node(P, f, j);
+            double u[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[c] = double(sU[(el * 4 + c) * Np + v]);
+            const double vx = u[1] / u[0], vy = u[2] / u[0];
+            const double p = (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+            const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * p / u[0]);
+            const double fs = !(sC[el].w & kCurvedBit)
+                                  ? double(sG[el][6 + 3 * f])
+                                  : double(a.geoC[(long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np +
+                                                  2 * NF3 + q]);
+            const double val = 0.5 * P1 * P1 * fs * lam;
+            vmax_blk = val > vmax_blk ? val : vmax_blk;
+        }
+        if (bad) atomicOr(a.flag, 1);
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(vmax_blk, off);
+            vmax_blk = o > vmax_blk ? o : vmax_blk;
+        }
+        if (lane == 0) sRed[wave] = vmax_blk;
+        __syncthreads();
+        if (tid == 0) {
+            double m = sRed[0];
+            for (int w = 1; w < kBlock / 64; ++w) m = sRed[w] > m ? sRed[w] : m;
+            atomicMax(a.vmax_out, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+// XCD-aware block order: block b runs on XCD b % 8; each XCD gets a
+// contiguous run of work items.
+__device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * chunk + blockIdx.x / 8; }
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
+    const int tile = xcd_item(a.chunk);
+    if (tile >= a.nblocks) return;
+    stage_tile<P>(a, tile);
+}
+
+// Batched meshes of one order: work item = (job, tile); a job is one mesh's
+// argument record for this stage.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs,
+                                                             const int2 *__restrict__ items,
+                                                             int nitems, int chunk) {
+    const int w = xcd_item(chunk);
+    if (w >= nitems) return;
+    const int2 it = items[w];
+    stage_tile<P>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -342,16 +463,23 @@ int mfma_elements_per_block(int P) {
     return with_order_m(P, [](auto PC) { return MShape<decltype(PC)::value>::EB; });
 }
 
-hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
-                             int stage, hipStream_t st) {
+int mfma_curved_bit() { return kCurvedBit; }
+
+static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                          const MfmaStep &step) {
     MfmaArgs a;
     a.K = m.K;
     a.stage = stage;
     a.mode = rhs ? 0 : 1;
+    a.cfl_mode = step.cfl_mode;
+    a.cfl_accum = step.cfl_accum;
     a.g = float(m.gamma);
     a.ra = float(rk_a(stage));
     a.rb = float(rk_b(stage));
-    for (int c = 0; c < 4; ++c) a.qinf[c] = float(m.qinf[c]);
+    a.ff = make_farfield<float>(m.gamma, m.qinf);
+    a.gamma = m.gamma;
+    a.cfl = m.cfl;
+    a.dt_fixed = step.dt_fixed;
     a.Uin = static_cast<const float *>(Uin);
     a.Uout = static_cast<float *>(Uout);
     a.R = static_cast<float *>(R);
@@ -362,12 +490,51 @@ hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void
     a.geoC = m.geoC;
     a.opsA = m.opsA;
     a.ops = m.ops32;
-    a.dt = m.scal + S_DT;
-    return with_order_m(m.P, [&](auto PC) {
-        constexpr int P = decltype(PC)::value;
-        using S = MShape<P>;
+    a.scal = m.scal;
+    a.vmax_in = step.vmax_in;
+    a.vmax_out = step.vmax_out;
+    a.flag = m.flag;
+    with_order_m(m.P, [&](auto PC) {
+        using S = MShape<decltype(PC)::value>;
         a.nblocks = (m.K + S::EB - 1) / S::EB;
         a.chunk = (a.nblocks + 7) / 8;
+        return 0;
+    });
+    return a;
+}
+
+size_t mfma_args_bytes() { return sizeof(MfmaArgs); }
+
+void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
+                    void *out) {
+    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step);
+    std::memcpy(out, &a, sizeof(a));
+}
+
+int mfma_tiles(const DevMesh &m) {
+    return with_order_m(m.P, [&](auto PC) {
+        using S = MShape<decltype(PC)::value>;
+        return (m.K + S::EB - 1) / S::EB;
+    });
+}
+
+hipError_t launch_stage_mfma_batch(int P, const void *jobs, const void *items, int nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int chunk = (nitems + 7) / 8;
+    return with_order_m(P, [&](auto PC) {
+        constexpr int PP = decltype(PC)::value;
+        hipLaunchKernelGGL((k_stage_mfma_batch<PP>), dim3(8 * chunk), dim3(kBlock), 0, st,
+                           static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
+                           chunk);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
+                             int stage, const MfmaStep &step, hipStream_t st) {
+    MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step);
+    return with_order_m(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
         hipLaunchKernelGGL((k_stage_mfma<P>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
         return hipGetLastError();
     });

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdg.so")
+# DG_LIBRARY may point at another build of the same library (same ABI).
+LIB_PATH = os.environ.get("DG_LIBRARY") or os.path.join(HERE, "libdg.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EGEOM, DG_ENONFINITE, DG_EDEVICE, DG_EBUSY = 0, -1, -2, -3, -4, -5, -6
 DG_FP64_PLAIN, DG_FP32 = 0, 2
@@ -25,7 +26,10 @@ PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP3
 EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_reference_operators", "dg_mesh_setup", "dg_mesh_destroy", "dg_buffer_bytes",
            "dg_rhs", "dg_step", "dg_run", "dg_totals", "dg_residual", "dg_viscosity",
-           "dg_set_kernel_timing", "dg_kernel_time", "dg_status")
+           "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_mesh_footprint",
+           "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
+           "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
+           "dg_status")
 
 
 class DGError(RuntimeError):
@@ -78,6 +82,17 @@ def lib():
         L.dg_viscosity.argtypes = [vp, vp, vp, vp]
         L.dg_status.argtypes = [vp, vp, C.POINTER(i)]
         L.dg_set_kernel_timing.argtypes = [vp, i]
+        L.dg_set_graphs.argtypes = [vp, i]
+        sz = C.c_size_t
+        L.dg_mesh_footprint.argtypes = [vp, C.POINTER(sz)]
+        L.dg_estimate_footprint.argtypes = [i, i, i, i, C.POINTER(sz)]
+        L.dg_batch_create.argtypes = [sz, i, C.POINTER(vp)]
+        L.dg_batch_destroy.argtypes = [vp]
+        L.dg_batch_admit.argtypes = [vp, vp, vp, vp, i, vp, C.POINTER(i)]
+        L.dg_batch_advance.argtypes = [vp, i, vp, C.POINTER(i)]
+        L.dg_batch_poll.argtypes = [vp, vp, vp, i, C.POINTER(i)]
+        L.dg_batch_slot_stats.argtypes = [vp, i, vp, C.POINTER(RunStats)]
+        L.dg_batch_release.argtypes = [vp, i]
         L.dg_kernel_time.argtypes = [vp, vp, C.POINTER(d), C.POINTER(C.c_long)]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or i
@@ -269,6 +284,9 @@ class Solver:
                                   _stream_handle(stream)))
         return eps
 
+    def set_graphs(self, enable=True):
+        _check(lib().dg_set_graphs(self._h, 1 if enable else 0))
+
     def set_kernel_timing(self, enable=True):
         _check(lib().dg_set_kernel_timing(self._h, 1 if enable else 0))
 
@@ -285,3 +303,71 @@ class Solver:
 
     def dofs(self):
         return 4 * self.Np * self.K
+
+    def footprint(self):
+        b = C.c_size_t()
+        _check(lib().dg_mesh_footprint(self._h, C.byref(b)))
+        return b.value
+
+
+def estimate_footprint(K, P, precision="fp32", av=False):
+    b = C.c_size_t()
+    _check(lib().dg_estimate_footprint(int(K), int(P), PRECISIONS[precision], 1 if av else 0,
+                                       C.byref(b)))
+    return b.value
+
+
+class Batch:
+    """Continuous batching of independent solves on one device (the
+    ``dg_batch_*`` ABI).  ``admit`` returns a slot id or None when the budget
+    or the slots are exhausted."""
+
+    def __init__(self, hbm_budget_bytes, max_slots):
+        self._h = C.c_void_p()
+        _check(lib().dg_batch_create(int(hbm_budget_bytes), int(max_slots), C.byref(self._h)))
+        self.max_slots = int(max_slots)
+        self._members = {}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dg_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, solver, U, nsteps, stream=None):
+        solver._check_state(U)
+        slot = C.c_int(-1)
+        rc = lib().dg_batch_admit(self._h, solver._h, C.c_void_p(U.data_ptr()),
+                                  C.c_void_p(solver.work.data_ptr()), int(nsteps),
+                                  _stream_handle(stream), C.byref(slot))
+        if rc == DG_EBUSY:
+            return None
+        _check(rc)
+        self._members[slot.value] = (solver, U)
+        return slot.value
+
+    def advance(self, max_steps, stream=None):
+        n = C.c_int(0)
+        _check(lib().dg_batch_advance(self._h, int(max_steps), _stream_handle(stream), C.byref(n)))
+        return n.value
+
+    def poll(self, stream=None):
+        buf = (C.c_int * self.max_slots)()
+        n = C.c_int(0)
+        _check(lib().dg_batch_poll(self._h, _stream_handle(stream), buf, self.max_slots, C.byref(n)))
+        return [buf[i] for i in range(min(n.value, self.max_slots))]
+
+    def stats(self, slot, stream=None):
+        st = RunStats()
+        _check(lib().dg_batch_slot_stats(self._h, int(slot), _stream_handle(stream), C.byref(st)))
+        return Stats(st.steps, st.status, st.t, st.dt_min, st.dt_max, tuple(st.totals),
+                     tuple(st.residual), st.wall_s, st.dof_updates_per_s)
+
+    def release(self, slot):
+        _check(lib().dg_batch_release(self._h, int(slot)))
+        return self._members.pop(slot, None)

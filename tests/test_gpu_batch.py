@@ -1,0 +1,93 @@
+"""Batching (continuous batching of independent solves): every result is the
+same bits as the same solve run alone, whatever else shares the launches."""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+def dg():
+    from paper_1208_4772_amd import dg as _dg
+    return _dg
+
+
+def make(kind, P, scale, precision="fp32", mach=None):
+    r, s = dg().reference_nodes(P)
+    case = meshgen.make_case(kind, r, s, scale=scale, P=P, mach=mach)
+    if kind == "airfoil":
+        case.av = False
+    sol = dg().Solver.from_case(case, precision)
+    return case, sol
+
+
+def run_alone(kind, P, scale, steps, precision="fp32", mach=None):
+    case, sol = make(kind, P, scale, precision, mach)
+    U = sol.state(case.U0)
+    st = sol.run(U, steps)
+    return U.double().cpu().numpy(), st
+
+
+def test_batch_results_equal_alone_bitwise():
+    import torch
+    reqs = [("cylinder", 4, 0.02, 7, "fp32", 0.38), ("vortex", 2, 1.0, 12, "fp32", None),
+            ("cylinder", 3, 0.03, 20, "fp32", 0.6), ("airfoil", 3, 0.01, 9, "fp32", 0.5),
+            ("cylinder", 5, 0.01, 11, "fp64", 0.3)]
+    late = ("vortex", 5, 0.3, 8, "fp32", None)
+    b = dg().Batch(1 << 34, 8)
+    live = {}
+    for kind, P, scale, steps, prec, mach in reqs:
+        case, sol = make(kind, P, scale, prec, mach)
+        U = sol.state(case.U0)
+        slot = b.admit(sol, U, steps)
+        assert slot is not None
+        live[slot] = (kind, P, scale, steps, prec, mach, sol, U)
+    finished = {}
+    admitted_late = False
+    while live:
+        n = b.advance(5)
+        assert n > 0
+        for slot in b.poll():
+            kind, P, scale, steps, prec, mach, sol, U = live.pop(slot)
+            st = b.stats(slot)
+            assert st.steps == steps and st.status == 0
+            finished[(kind, P, scale, steps, prec)] = (U.double().cpu().numpy(), st)
+            b.release(slot)
+            if not admitted_late:
+                kind2, P2, sc2, st2, pr2, m2 = late
+                case, sol2 = make(kind2, P2, sc2, pr2, m2)
+                U2 = sol2.state(case.U0)
+                s2 = b.admit(sol2, U2, st2)
+                live[s2] = (kind2, P2, sc2, st2, pr2, m2, sol2, U2)
+                admitted_late = True
+    torch.cuda.synchronize()
+    assert len(finished) == len(reqs) + 1
+    for (kind, P, scale, steps, prec), (Ub, stb) in finished.items():
+        mach = {r[:5]: r[5] for r in reqs + [late]}[(kind, P, scale, steps, prec)]
+        Ua, sta = run_alone(kind, P, scale, steps, prec, mach)
+        assert np.array_equal(Ua, Ub), (kind, P, np.abs(Ua - Ub).max())
+        assert sta.t == stb.t and sta.dt_min == stb.dt_min
+
+
+def test_admission_by_footprint():
+    case, s1 = make("cylinder", 4, 0.02)
+    _, s2 = make("cylinder", 4, 0.02)
+    f1, f2 = s1.footprint(), s2.footprint()
+    assert f1 > 0
+    assert dg().estimate_footprint(case.K, 4) >= f1
+    b = dg().Batch(f1 + f2 // 2, 4)
+    U1 = s1.state(case.U0)
+    U2 = s2.state(case.U0)
+    a = b.admit(s1, U1, 3)
+    assert a is not None
+    assert b.admit(s2, U2, 3) is None          # over budget: stays queued
+    while b.advance(10):
+        pass
+    assert b.poll() == [a]
+    b.release(a)
+    c = b.admit(s2, U2, 3)                      # room again
+    assert c is not None
+    slots = dg().Batch(1 << 34, 1)
+    assert slots.admit(s1, U1, 2) is not None
+    assert slots.admit(s2, U2, 2) is None       # no free slot
