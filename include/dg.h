@@ -62,8 +62,13 @@ enum dg_status {
 
 enum dg_precision {
     DG_FP64_PLAIN = 0,   /* FP64 throughout; straightforward VALU kernels */
-    DG_FP32 = 2          /* FP32 state and fused stage kernel; FP64 setup,
+    DG_FP32 = 2,         /* FP32 state and fused stage kernel; FP64 setup,
                             time step and reductions */
+    DG_FP32_BF16X3 = 3   /* as DG_FP32, but the stage's matrix product runs as
+                            three BF16 products of hi/lo splits,
+                            A_hi B_hi + A_hi B_lo + A_lo B_hi, accumulated in
+                            FP32 (about 16 significant bits per product;
+                            fluxes, face terms and the update stay FP32) */
 };
 
 enum dg_bc { DG_BC_INTERIOR = 0, DG_BC_WALL = 1, DG_BC_FARFIELD = 2 };

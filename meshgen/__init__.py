@@ -7,6 +7,6 @@ from .meshes import (BC_FARFIELD, BC_INTERIOR, BC_WALL, FACE_VERTS, Mesh,  # noq
                      connect, cylinder_annulus, naca4_ogrid, naca4_thickness,
                      naca_point, node_coordinates, periodic_square,
                      permute_elements)
-from .flows import (GAMMA, freestream_state, isentropic_vortex,  # noqa: F401
-                    primitive_to_conserved, uniform)
+from .flows import (GAMMA, cylinder_potential, freestream_state,  # noqa: F401
+                    isentropic_vortex, primitive_to_conserved, uniform)
 from .cases import CASES, make_case  # noqa: F401

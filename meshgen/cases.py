@@ -52,8 +52,11 @@ def _np_of(P):
 
 
 def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
-              mach: float | None = None, steps: int | None = None) -> Case:
-    """Build one of ``CASES``.  ``scale`` < 1 shrinks the element count."""
+              mach: float | None = None, steps: int | None = None,
+              start: str = "freestream") -> Case:
+    """Build one of ``CASES``.  ``scale`` < 1 shrinks the element count.
+    ``start="potential"`` starts the cylinder from the wall-compatible
+    potential flow instead of the impulsive freestream."""
     r = np.asarray(r, dtype=np.float64)
     s = np.asarray(s, dtype=np.float64)
     if name == "vortex":
@@ -74,7 +77,10 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
         x, y = meshes.node_coordinates(mesh, r, s)
         M = 0.38 if mach is None else mach
         q = flows.freestream_state(M, 0.0)
-        U0 = flows.uniform((mesh.K, x.shape[1]), q)
+        if start == "potential":
+            U0 = np.ascontiguousarray(flows.cylinder_potential(x, y, M))
+        else:
+            U0 = flows.uniform((mesh.K, x.shape[1]), q)
         return Case(name, P, mesh, x, y, U0, q, steps=2000 if steps is None else steps,
                     info=dict(mach=M, alpha=0.0))
     if name == "airfoil":

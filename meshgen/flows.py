@@ -26,6 +26,27 @@ def freestream_state(mach: float, alpha_deg: float = 0.0, gamma=GAMMA):
     return np.array([1.0, u, v, p / (gamma - 1.0) + 0.5 * (u * u + v * v)])
 
 
+def cylinder_potential(x, y, mach: float, radius: float = 1.0, gamma=GAMMA):
+    """Wall-compatible start for flow past a cylinder of the given radius at
+    the origin: the incompressible potential-flow velocity (freestream
+    (mach, 0), zero normal velocity on the wall) with density and pressure
+    from the isentropic energy relation c^2 = 1 + (gamma-1)/2 (M^2 - |v|^2)
+    (rho = c^(2/(gamma-1)), p = rho^gamma / gamma; freestream rho = c = 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r2 = (x * x + y * y) / (radius * radius)
+    th = np.arctan2(y, x)
+    ur = mach * (1.0 - 1.0 / r2) * np.cos(th)
+    ut = -mach * (1.0 + 1.0 / r2) * np.sin(th)
+    u = ur * np.cos(th) - ut * np.sin(th)
+    v = ur * np.sin(th) + ut * np.cos(th)
+    c2 = 1.0 + 0.5 * (gamma - 1.0) * (mach * mach - (u * u + v * v))
+    if np.any(c2 <= 0):
+        raise ValueError("Mach number too high for the isentropic potential start")
+    rho = c2 ** (1.0 / (gamma - 1.0))
+    return primitive_to_conserved(rho, u, v, rho ** gamma / gamma, gamma)
+
+
 def uniform(shape_KNp, q):
     """Fill (K,4,Np) with the constant state q (4,)."""
     K, Np = shape_KNp

@@ -158,8 +158,8 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     if (!d) return fail(DG_EINVAL, "desc is NULL");
     if (d->P < 1 || d->P > 5) return fail(DG_EINVAL, "order P must be 1..5");
     if (d->K < 1) return fail(DG_EINVAL, "K must be >= 1");
-    if (d->precision != DG_FP64_PLAIN && d->precision != DG_FP32)
-        return fail(DG_EINVAL, "precision must be DG_FP64_PLAIN or DG_FP32");
+    if (d->precision != DG_FP64_PLAIN && d->precision != DG_FP32 && d->precision != DG_FP32_BF16X3)
+        return fail(DG_EINVAL, "precision must be DG_FP64_PLAIN, DG_FP32 or DG_FP32_BF16X3");
     if (!(d->gamma > 1.0)) return fail(DG_EINVAL, "gamma must be > 1");
     if (!(d->cfl > 0.0)) return fail(DG_EINVAL, "cfl must be > 0");
     if (!d->EToE || !d->EToF || !d->bc || !d->x || !d->y) return fail(DG_EINVAL, "null mesh array");
@@ -210,7 +210,8 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     dm.P = P;
     dm.Np = Np;
     dm.Nfp = Nfp;
-    dm.fp32 = d->precision == DG_FP32;
+    dm.fp32 = d->precision == DG_FP32 || d->precision == DG_FP32_BF16X3;
+    dm.bf3 = d->precision == DG_FP32_BF16X3;
     dm.av = d->av_enable != 0;
     dm.gamma = d->gamma;
     dm.cfl = d->cfl;
@@ -312,6 +313,16 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         std::vector<float> opsA(nA);
         mfma_fill_opsA(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsA.data());
         SETUP_TRY(hipMemcpyAsync(opsA_d, opsA.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
+        if (dm.bf3) {
+            const size_t nB = mfma_opsB_words(P);
+            unsigned *opsB_d;
+            if ((rc = m->alloc(&opsB_d, nB))) return cleanup(rc);
+            std::vector<unsigned> opsB(nB);
+            mfma_fill_opsB(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsB.data());
+            SETUP_TRY(hipMemcpyAsync(opsB_d, opsB.data(), sizeof(unsigned) * nB, hipMemcpyHostToDevice, st));
+            SETUP_TRY(hipStreamSynchronize(st));
+            dm.opsB = opsB_d;
+        }
         SETUP_TRY(launch_affine_flags(dm, flags_d, st));
         std::vector<int> flags(K), cidx(K);
         SETUP_TRY(hipMemcpyAsync(flags.data(), flags_d, sizeof(int) * K, hipMemcpyDeviceToHost, st));
@@ -658,11 +669,12 @@ int dg_mesh_footprint(const dg_mesh *m, size_t *bytes) {
 int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *bytes) {
     if (!bytes || K < 1 || P < 1 || P > 5) return fail(DG_EINVAL, "bad arguments");
     const size_t Np = size_t(n_nodes(P)), Nfp = size_t(P + 1), k = size_t(K);
-    const size_t s = precision == DG_FP32 ? 4 : 8;
+    const bool f32 = precision == DG_FP32 || precision == DG_FP32_BF16X3;
+    const size_t s = f32 ? 4 : 8;
     size_t b = k * (3 + 1) * 4;                                   // nbr, finfo
     b += k * Np * 2 * 8;                                          // node coordinates
     b += k * (4 * Np + 9 * Nfp + Np + 1) * 8;                     // FP64 geometry, mass weights, eps_max
-    if (precision == DG_FP32)
+    if (f32)
         b += k * (4 * Np + 9 * Nfp + 1) * 4 + k * (4 + 1 + 1) * 4 + k * 16 * 4  // FP32 copies, conn, flags
              + k * (4 * Np + 9 * Nfp) * 4;                        // curved records (upper bound)
     const size_t state = k * 4 * Np * s;
@@ -688,6 +700,7 @@ struct Slot {
 // the work list of (job, tile) items.
 struct Group {
     int P = 0;
+    bool bf3 = false;
     std::vector<int> slots;
     void *jobs = nullptr;
     size_t jobs_cap = 0;
@@ -726,12 +739,14 @@ int rebuild(dg_batch *b, hipStream_t st) {
     std::vector<Group> old;
     old.swap(b->groups);
     b->singles.clear();
-    for (int P = 1; P <= 5; ++P) {
+    for (int key = 0; key < 10; ++key) {
         Group g;
-        g.P = P;
+        g.P = 1 + key % 5;
+        g.bf3 = key >= 5;
         for (size_t i = 0; i < b->slots.size(); ++i) {
             const Slot &s = b->slots[i];
-            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == P) g.slots.push_back(int(i));
+            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == g.P && s.mesh->dm.bf3 == g.bf3)
+                g.slots.push_back(int(i));
         }
         if (!g.slots.empty()) b->groups.push_back(std::move(g));
     }
@@ -742,7 +757,7 @@ int rebuild(dg_batch *b, hipStream_t st) {
     // reuse old allocations where they are large enough
     for (Group &g : b->groups) {
         for (Group &o : old)
-            if (o.P == g.P) {
+            if (o.P == g.P && o.bf3 == g.bf3) {
                 g.jobs = o.jobs;
                 g.jobs_cap = o.jobs_cap;
                 g.items = o.items;
@@ -817,7 +832,7 @@ int batch_step(dg_batch *b, int ps, hipStream_t st) {
     for (int s5 = 0; s5 < 5; ++s5)
         for (const Group &g : b->groups) {
             const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * g.slots.size() * rec;
-            HIP_TRY(launch_stage_mfma_batch(g.P, jobs, g.items, g.nitems, st));
+            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, jobs, g.items, g.nitems, st));
         }
     for (int i : b->singles) {
         Slot &s = b->slots[i];

@@ -38,6 +38,20 @@ struct FaceTable {
     }
 };
 
+// Face entries q = f * (P+1) + j that land on each node: up to two (the
+// three corners lie on two faces), packed as (q0 + 1) | (q1 + 1) << 8 with 0
+// for "none".
+template <int P>
+struct NodeFaceTable {
+    int v[(P + 1) * (P + 2) / 2];
+    constexpr NodeFaceTable() : v() {
+        for (int q = 0; q < 3 * (P + 1); ++q) {
+            const int n = face_node(P, q / (P + 1), q % (P + 1));
+            v[n] = v[n] == 0 ? q + 1 : (v[n] | (q + 1) << 8);
+        }
+    }
+};
+
 // Packed face information of an element: 4 bits per face, low 2 bits the
 // neighbour's face id, high 2 bits the boundary code.
 __host__ __device__ inline int face_nbr_face(int info, int f) { return (info >> (4 * f)) & 3; }

@@ -21,6 +21,7 @@ enum Scalar {
 struct DevMesh {
     int K = 0, P = 0, Np = 0, Nfp = 0;
     bool fp32 = false;
+    bool bf3 = false;              // FP32 handle whose stage product runs as BF16x3
     bool av = false;
     double gamma = 1.4, cfl = 0.5;
     double qinf[4] = {1, 0, 0, 2.5};
@@ -41,6 +42,7 @@ struct DevMesh {
     const int *cidx = nullptr;      // [K] curved slot or -1
     const float *geoC = nullptr;    // [Kc][4 Np + 9 Nfp] curved geometry
     const float *opsA = nullptr;    // MFMA A operand table
+    const unsigned *opsB = nullptr; // BF16x3 A operand table (hi and lo splits)
     int Kc = 0;
     int ncu = 256;                  // compute units of the device
     int blocks_per_cu = 4;          // persistent blocks per CU (matrix-core kernel)
@@ -95,11 +97,14 @@ size_t mfma_args_bytes();
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
                     void *out);
 int mfma_tiles(const DevMesh &m);
-hipError_t launch_stage_mfma_batch(int P, const void *jobs, const void *items, int nitems, hipStream_t st);
+hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void *items, int nitems,
+                                   hipStream_t st);
 // CFL bound of state U (FP64) into *slot as a bit pattern; raises *flag on bad states
 hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st);
 size_t mfma_opsA_floats(int P);
 void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out);
+size_t mfma_opsB_words(int P);
+void mfma_fill_opsB(int P, const double *Dr, const double *Ds, const double *LIFT, unsigned *out);
 int mfma_elements_per_block(int P);
 // setup: flags[k] = 1 if element k's metric terms, normals and Fscale are
 // constant to 1e-10 relative (a straight element)

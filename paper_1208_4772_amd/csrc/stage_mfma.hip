@@ -7,20 +7,22 @@
 // and the whole right-hand side of a field becomes one product
 //   rhs = [-Dr  -Ds  LIFT] (Np x (2Np + 3Nfp))  .  [F'; G'; Fscale (n.F - F*)].
 // The kernel forms that product for groups of 4 elements x 4 fields = 16
-// columns on the MFMA unit (A operand staged per block in LDS, B operand
-// built in LDS).  A curved element keeps its per-node metrics: its F', G'
-// rows are zeroed (the product then yields only the LIFT term) and its
-// volume term is formed separately with per-node metrics on the VALUs.
+// columns on the MFMA unit (A operand read from global memory, where the
+// same few KB serve every block from the caches; B operand built in LDS).
+// A curved element keeps its per-node metrics: its F', G' rows are zeroed
+// (the product then yields only the LIFT term) and its volume term is
+// formed separately with per-node metrics on the VALUs.
 //
 // Memory: the element tile's state, the Runge-Kutta register and the
 // outputs move as one coalesced 16-byte access per lane; per-element
 // geometry (13 floats for an affine element) and connectivity (16 bytes)
-// likewise; the only scattered reads are the neighbours' face traces
-// (neighbours inside the tile come from LDS).  Blocks are remapped so that
-// each XCD sweeps a contiguous range of tiles, which keeps recently loaded
-// neighbours in that XCD's L2.  Registers and LDS are kept low (A operand
-// in LDS, the result staged in the B operand's own space) so that five to
-// six blocks share a CU and hide each other's memory latency.
+// likewise; the only scattered reads are the neighbours' face traces, which
+// each thread issues at the start for the face nodes it will handle, so that
+// their latency overlaps the tile load and the pointwise phase.  Blocks are
+// remapped so that each XCD sweeps a contiguous range of tiles, which keeps
+// recently loaded neighbours in that XCD's L2.  LDS per block is kept small
+// (the result is staged in the B operand's own space) so that several
+// blocks share a CU and hide each other's memory latency.
 //
 // Time step: in a fused run the last stage also reduces the CFL bound of
 // the new state (FP64 arithmetic) into a device slot, and the next step's
@@ -37,23 +39,29 @@ namespace dg {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 constexpr int kCurvedBit = 1 << 12;   // in the packed face-info word
 
-template <int P>
+// BF3: the product runs as three BF16 products (v_mfma_f32_16x16x32_bf16)
+// of hi/lo splits, K padded to multiples of 32.
+template <int P, bool BF3 = false>
 struct MShape {
     static constexpr int Np = (P + 1) * (P + 2) / 2;
     static constexpr int Nfp = P + 1;
     static constexpr int NF3 = 3 * Nfp;
     static constexpr int KV = 2 * Np + NF3;     // contraction length
-    static constexpr int KS = (KV + 3) / 4;     // MFMA k-steps (K = 4 each)
-    static constexpr int KP = 4 * KS;           // padded contraction length
+    static constexpr int KS = (KV + 3) / 4;     // FP32 MFMA k-steps (K = 4 each)
+    static constexpr int KS32 = (KV + 31) / 32; // BF16 MFMA k-steps (K = 32 each)
+    static constexpr int KP = BF3 ? 32 * KS32 : 4 * KS;  // padded contraction length
     static constexpr int MT = (Np + 15) / 16;   // 16-row output tiles
     static constexpr int EW = 64 / Np;          // elements per wavefront (pointwise phase)
     static constexpr int EB = 4 * EW;           // elements per block
     static constexpr int NT = EB / 4;           // 16-column groups per block
     static constexpr int TF = EB * 4 * Np;      // state floats per block (<= 1024)
+    static constexpr int TPT = (EB * NF3 + 255) / 256;  // face-node tasks per thread
     static_assert(TF <= 4 * kBlock, "one float4 per thread covers the tile");
     static_assert(16 * Np <= 16 * KP, "a column group's result fits in its B block");
 };
@@ -81,14 +89,70 @@ struct MfmaArgs {
     int *__restrict__ flag;
 };
 
+// Node id of face node j of face f without branches (selects only).
+template <int P>
+__device__ __forceinline__ int face_node_sel(int f, int j) {
+    const int n = f == 0 ? 0 : (f == 1 ? j : P - j);
+    const int off = f == 0 ? j : (f == 1 ? P - j : 0);
+    return n * (P + 1) - ((n * (n - 1)) >> 1) + off;
+}
+
+// Lax-Friedrichs face term of one face-node task, scaled by Fscale, into the
+// B operand.  CURVED: the tile holds curved elements, whose normals and
+// Fscale are per face node.
+template <int P, bool BF3, bool CURVED>
+__device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, const int el, const int q,
+                                          const float (&upn)[4], const float *sU, const float (*sG)[16],
+                                          const int4 *sC, const int *sFN, const float (*sPrim)[4],
+                                          float *sBflat) {
+    using S = MShape<P, BF3>;
+    constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KP = S::KP;
+    const int f = q / Nfp;
+    const int vm = sFN[q];
+    float um[4], up[4], d[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) um[c] = sU[(el * 4 + c) * Np + vm];
+    const int4 cv = sC[el];
+    float nx, ny, fs;
+    if (CURVED && (cv.w & kCurvedBit)) {
+        const float *gc = a.geoC + (long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np;
+        nx = gc[q];
+        ny = gc[NF3 + q];
+        fs = gc[2 * NF3 + q];
+    } else {
+        nx = sG[el][4 + 3 * f];
+        ny = sG[el][5 + 3 * f];
+        fs = sG[el][6 + 3 * f];
+    }
+    const int code = face_bc(cv.w, f);
+    if (code == BC_INTERIOR) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) up[c] = upn[c];
+    } else {
+        ghost_state(a.g, code, um, nx, ny, a.ff, up);
+    }
+    // n.F(U-) and its wave speed from the pointwise phase's primitives
+    const f32x4 pm = *reinterpret_cast<const f32x4 *>(sPrim[el * Np + vm]);
+    const float vnm = (um[1] * nx + um[2] * ny) * pm[0];
+    const float fm[4] = {um[0] * vnm, um[1] * vnm + pm[1] * nx, um[2] * vnm + pm[1] * ny, (um[3] + pm[1]) * vnm};
+    const float lm = fabsf(vnm) + pm[2];
+    float fp[4], lp;
+    normal_flux(a.g, up, nx, ny, fp, lp);
+    const float lam = lm > lp ? lm : lp;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
+    const f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
+    *reinterpret_cast<f32x4 *>(&sBflat[((el >> 2) * KP + 2 * Np + q) * 16 + (el & 3) * 4]) = jv;
+}
+
 // One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
 // arguments (single mesh) or in a device job table (batched meshes); its
 // fields are uniform across the block.
-template <int P>
+template <int P, bool BF3>
 __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
-    using S = MShape<P>;
-    constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KP = S::KP, MT = S::MT;
-    constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF;
+    using S = MShape<P, BF3>;
+    constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KS32 = S::KS32, KP = S::KP, MT = S::MT;
+    constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF, TPT = S::TPT;
 
     // ---- time step of this stage
     double dtd = 0.0;
@@ -112,35 +176,54 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
 
     __shared__ float sU[TF];
     __shared__ float sB[NT][KP][16];    // B operand; afterwards the result of that column group
-    __shared__ float sA[MT * KS * 64];
     __shared__ float sG[EB][16];
     __shared__ int4 sC[EB];
     __shared__ int sAny;
-    __shared__ double sRed[kBlock / 64];
-    __shared__ int sFN[NF3];          // face node ids, face-major, counter-clockwise
-    __shared__ float sPrim[EB][Np][4];  // 1/rho, p, sound speed, unused (pointwise phase)
+    __shared__ float sRed[kBlock / 64];
+    __shared__ int sFN[NF3];              // face node ids, face-major, counter-clockwise
+    __shared__ float sPrim[EB * Np][4];   // 1/rho, p, sound speed, unused (pointwise phase)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long base = k0 * 4 * Np;
     const int nflt = nel * 4 * Np;
+    const int ntask = nel * NF3;
     // result (element el, field c, node i) lives in its column group's block
     auto res = [&](int el, int off) -> float & { return (&sB[el >> 2][0][0])[(el & 3) * 4 * Np + off]; };
 
-    // ---- coalesced tile loads: state, RK register, geometry, connectivity, A
-    f32x4 u4 = {0, 0, 0, 0}, r4 = {0, 0, 0, 0};
-    const bool flat_ok = 4 * tid < nflt;
-    if (flat_ok) {
-        u4 = *reinterpret_cast<const f32x4 *>(a.Uin + base + 4 * tid);
-        if (a.mode && a.stage > 0) r4 = *reinterpret_cast<const f32x4 *>(a.R + base + 4 * tid);
+    // ---- loads.  Every address is clamped into the tile so that the loads
+    // need no branches; the neighbour face traces for the face-node tasks
+    // this thread will handle (task = element * 3 Nfp + face node; tasks tid,
+    // tid + 256, ...) are requested as soon as the connectivity arrives, so
+    // their latency overlaps the tile load and the pointwise phase.
+    int4 tconn[TPT];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const int task = min(tid + t * kBlock, ntask - 1);
+        tconn[t] = a.conn[k0 + task / NF3];
     }
-    if (tid < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid] = a.geoA[k0 * 4 + tid];
-    if (tid < nel) sC[tid] = a.conn[k0 + tid];
-    for (int z = tid; z < MT * KS * 16; z += kBlock)
-        reinterpret_cast<f32x4 *>(sA)[z] = reinterpret_cast<const f32x4 *>(a.opsA)[z];
+    const bool flat_ok = 4 * tid < nflt;
+    const f32x4 u4 = *reinterpret_cast<const f32x4 *>(a.Uin + base + (flat_ok ? 4 * tid : 0));
+    const float4 g4 = a.geoA[k0 * 4 + min(tid, 4 * nel - 1)];
+    const int4 c4 = a.conn[k0 + min(tid, nel - 1)];
+    float upn[TPT][4];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const int task = min(tid + t * kBlock, ntask - 1);
+        const int q = task % NF3, f = q / Nfp, j = q - f * Nfp;
+        const int4 cv = tconn[t];
+        const bool inner = face_bc(cv.w, f) == BC_INTERIOR;
+        const int kn = inner ? (f == 0 ? cv.x : (f == 1 ? cv.y : cv.z)) : int(k0);
+        const int vp = face_node_sel<P>(face_nbr_face(cv.w, f), Nfp - 1 - j);
+        const float *src = a.Uin + (long)kn * 4 * Np + vp;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) upn[t][c] = src[c * Np];
+    }
+    f32x4 r4 = {0, 0, 0, 0};
+    if (a.mode && a.stage > 0) r4 = *reinterpret_cast<const f32x4 *>(a.R + base + (flat_ok ? 4 * tid : 0));
+
     if (tid == 0) sAny = 0;
-    if (tid < NF3) sFN[tid] = face_node(P, tid / Nfp, tid % Nfp);
-    if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
+    if (tid < NF3) sFN[tid] = face_node_sel<P>(tid / Nfp, tid % Nfp);
     if constexpr (KP > S::KV) {
         constexpr int PADN = (KP - S::KV) * 16;
         for (int z = tid; z < NT * PADN; z += kBlock) {
@@ -148,6 +231,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             sB[t][S::KV + rem / 16][rem % 16] = 0.f;
         }
     }
+    if (tid < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid] = g4;
+    if (tid < nel) sC[tid] = c4;
+    if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
     __syncthreads();
 
     // ---- pointwise fluxes (lane = element * Np + node within the wavefront)
@@ -164,7 +250,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         const float p = pressure_ir(a.g, u, ir);
         const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
         const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
-        *reinterpret_cast<f32x4 *>(&sPrim[eln][in][0]) = f32x4{ir, p, fsqrt(a.g * p * ir), 0.f};
+        *reinterpret_cast<f32x4 *>(sPrim[eln * Np + in]) = f32x4{ir, p, fsqrt(a.g * p * ir), 0.f};
         const int t = eln >> 2, col = (eln & 3) * 4;
         f32x4 f, gg;
         curved_lane = sC[eln].w & kCurvedBit;
@@ -187,56 +273,19 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         *reinterpret_cast<f32x4 *>(&sB[t][Np + in][col]) = gg;
     }
     __syncthreads();
-    // ---- Lax-Friedrichs flux at the face nodes (task = element * 3Nfp + face node)
-    for (int task = tid; task < nel * NF3; task += kBlock) {
-        const int el = task / NF3, q = task - el * NF3;
-        const int f = q / Nfp, j = q - f * Nfp;
-        const int vm = sFN[q];
-        float um[4], up[4], d[4];
+    const bool any_curved = sAny;
+
+    // ---- Lax-Friedrichs flux at the face nodes
 #pragma unroll
-        for (int c = 0; c < 4; ++c) um[c] = sU[(el * 4 + c) * Np + vm];
-        const int4 cv = sC[el];
-        float nx, ny, fs;
-        if (!(cv.w & kCurvedBit)) {
-            nx = sG[el][4 + 3 * f];
-            ny = sG[el][5 + 3 * f];
-            fs = sG[el][6 + 3 * f];
-        } else {
-            const float *gc = a.geoC + (long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np;
-            nx = gc[q];
-            ny = gc[NF3 + q];
-            fs = gc[2 * NF3 + q];
+    for (int t = 0; t < TPT; ++t) {
+        const int task = tid + t * kBlock;
+        if (task < ntask) {
+            const int el = task / NF3, q = task - el * NF3;
+            if (any_curved)
+                face_task<P, BF3, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
+            else
+                face_task<P, BF3, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
         }
-        const int code = face_bc(cv.w, f);
-        if (code == BC_INTERIOR) {
-            const long kn = f == 0 ? cv.x : (f == 1 ? cv.y : cv.z);
-            const int vp = sFN[face_nbr_face(cv.w, f) * Nfp + Nfp - 1 - j];
-            const long ln = kn - k0;
-            if (ln >= 0 && ln < nel) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) up[c] = sU[(ln * 4 + c) * Np + vp];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) up[c] = a.Uin[(kn * 4 + c) * Np + vp];
-            }
-        } else {
-            ghost_state(a.g, code, um, nx, ny, a.ff, up);
-        }
-        {
-            // n.F(U-) and its wave speed from the pointwise phase's primitives
-            const f32x4 pm = *reinterpret_cast<const f32x4 *>(&sPrim[el][vm][0]);
-            const float vnm = (um[1] * nx + um[2] * ny) * pm[0];
-            float fm[4] = {um[0] * vnm, um[1] * vnm + pm[1] * nx, um[2] * vnm + pm[1] * ny,
-                           (um[3] + pm[1]) * vnm};
-            const float lm = fabsf(vnm) + pm[2];
-            float fp[4], lp;
-            normal_flux(a.g, up, nx, ny, fp, lp);
-            const float lam = lm > lp ? lm : lp;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
-        }
-        const f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
-        *reinterpret_cast<f32x4 *>(&sB[el >> 2][2 * Np + q][(el & 3) * 4]) = jv;
     }
     __syncthreads();
 
@@ -244,7 +293,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     // in registers; their F/G rows are then cleared so the product gives
     // only the LIFT term
     float vol[4] = {0, 0, 0, 0};
-    const bool any_curved = sAny;
     if (any_curved) {
         if (curved_lane) {
             const float *gc = a.geoC + (long)a.cidx[k0 + eln] * (4 * Np + 9 * Nfp);
@@ -281,25 +329,62 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     // w, w+4, ...; result row = node, column = 4 * element + field.  The
     // wavefront writes the result over its own (fully consumed) B block.
     for (int t = wave; t < NT; t += 4) {
-        // two independent accumulation chains per output tile (even and odd
-        // k-steps) halve the dependent-MFMA latency
         f32x4 acc[MT], acc2[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             acc[mt] = f32x4{0, 0, 0, 0};
             acc2[mt] = f32x4{0, 0, 0, 0};
         }
+        if constexpr (!BF3) {
+            // A operand fragments straight from global memory (the same few
+            // KB for every block, so they stay in the caches)
+            float av[MT * KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float b = sB[t][4 * ks + (lane >> 4)][lane & 15];
+            for (int z = 0; z < MT * KS; ++z) av[z] = a.opsA[z * 64 + lane];
+            // two independent accumulation chains per output tile (even and
+            // odd k-steps) halve the dependent-MFMA latency
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                if (ks & 1)
-                    acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[(mt * KS + ks) * 64 + lane], b,
-                                                                    acc2[mt], 0, 0, 0);
-                else
-                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[(mt * KS + ks) * 64 + lane], b,
-                                                                   acc[mt], 0, 0, 0);
+            for (int ks = 0; ks < KS; ++ks) {
+                const float b = sB[t][4 * ks + (lane >> 4)][lane & 15];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    if (ks & 1)
+                        acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt * KS + ks], b, acc2[mt], 0, 0, 0);
+                    else
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt * KS + ks], b, acc[mt], 0, 0, 0);
+                }
+            }
+        } else {
+            // BF16x3: A = Ah + Al (split on the host), B = Bh + Bl (split
+            // here, round to nearest even), AB ~ Ah Bh + (Ah Bl + Al Bh); the
+            // dropped Al Bl and the split residues are O(2^-16) |A||B|.
+            // Lane l holds k-slots 8 (l / 16) + i, i < 8, of row/column l % 16
+            // in both operands, so the slot-to-k assignment is the same on
+            // both sides of the product.
+            const u32x4 *opsB = reinterpret_cast<const u32x4 *>(a.opsA);
+            u32x4 ah[MT * KS32], al[MT * KS32];
+#pragma unroll
+            for (int z = 0; z < MT * KS32; ++z) {
+                ah[z] = opsB[(2 * z) * 64 + lane];
+                al[z] = opsB[(2 * z + 1) * 64 + lane];
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS32; ++ks) {
+                bf16x8 bh, bl;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float b = sB[t][32 * ks + 8 * (lane >> 4) + i][lane & 15];
+                    bh[i] = __bf16(b);
+                    bl[i] = __bf16(b - float(bh[i]));
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[mt * KS32 + ks]);
+                    const bf16x8 Al = __builtin_bit_cast(bf16x8, al[mt * KS32 + ks]);
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bh, acc[mt], 0, 0, 0);
+                    acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bl, acc2[mt], 0, 0, 0);
+                    acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bh, acc2[mt], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
@@ -342,48 +427,49 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         }
     }
     if (a.cfl_accum) {
-        // CFL bound and state check of the new state (FP64 arithmetic)
+        // CFL bound and state check of the new state: one lane per node; the
+        // node's wave speed times the largest Fscale of the faces it lies on
+        // (FP32 like the state; the maximum is exact and dt = cfl / max is
+        // formed in FP64 by the next step's first stage)
         __syncthreads();
-        const double g = a.gamma, P1 = P + 1.0;
-        double vmax_blk = 0.0;
+        float vmax_lane = 0.f;
         int bad = 0;
         if (node_ok) {
-            double u[4];
+            float u[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = double(sU[(eln * 4 + c) * Np + in]);
-            const double p = (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
-            if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+            for (int c = 0; c < 4; ++c) u[c] = sU[(eln * 4 + c) * Np + in];
+            const float ir = rcp(u[0]);
+            const float vx = u[1] * ir, vy = u[2] * ir;
+            const float p = pressure_ir(a.g, u, ir);
+            if (!(u[0] > 0.f) || !(p > 0.f) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
                 !isfinite(p))
                 bad = 1;
+            constexpr NodeFaceTable<P> kNF;
+            const int nq = kNF.v[in];
+            if (nq) {
+                const int q0 = (nq & 255) - 1, q1 = (nq >> 8) - 1;
+                float fs;
+                if (!curved_lane) {
+                    fs = sG[eln][6 + 3 * (q0 / Nfp)];
+                    if (q1 >= 0) fs = fmaxf(fs, sG[eln][6 + 3 * (q1 / Nfp)]);
+                } else {
+                    const float *gf = a.geoC + (long)a.cidx[k0 + eln] * (4 * Np + 9 * Nfp) + 4 * Np + 2 * NF3;
+                    fs = gf[q0];
+                    if (q1 >= 0) fs = fmaxf(fs, gf[q1]);
+                }
+                const float lam = fsqrt(vx * vx + vy * vy) + fsqrt(a.g * p * ir);
+                vmax_lane = 0.5f * float((P + 1) * (P + 1)) * fs * lam;
+            }
         }
-        for (int task = tid; task < nel * NF3; task += kBlock) {
-            const int el = task / NF3, q = task - el * NF3;
-            const int f = q / Nfp, j = q - f * Nfp;
-            const int v = face_node(P, f, j);
-            double u[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = double(sU[(el * 4 + c) * Np + v]);
-            const double vx = u[1] / u[0], vy = u[2] / u[0];
-            const double p = (g - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
-            const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * p / u[0]);
-            const double fs = !(sC[el].w & kCurvedBit)
-                                  ? double(sG[el][6 + 3 * f])
-                                  : double(a.geoC[(long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np +
-                                                  2 * NF3 + q]);
-            const double val = 0.5 * P1 * P1 * fs * lam;
-            vmax_blk = val > vmax_blk ? val : vmax_blk;
-        }
-        if (bad) atomicOr(a.flag, 1);
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(vmax_blk, off);
-            vmax_blk = o > vmax_blk ? o : vmax_blk;
-        }
-        if (lane == 0) sRed[wave] = vmax_blk;
+        if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
+        for (int off = 32; off > 0; off >>= 1) vmax_lane = fmaxf(vmax_lane, __shfl_xor(vmax_lane, off));
+        if (lane == 0) sRed[wave] = vmax_lane;
         __syncthreads();
         if (tid == 0) {
-            double m = sRed[0];
-            for (int w = 1; w < kBlock / 64; ++w) m = sRed[w] > m ? sRed[w] : m;
-            atomicMax(a.vmax_out, (unsigned long long)__double_as_longlong(m));
+            float m = sRed[0];
+            for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sRed[w]);
+            // a NaN speed leaves m unordered; the flag above reports it
+            atomicMax(a.vmax_out, (unsigned long long)__double_as_longlong(double(m)));
         }
     }
 }
@@ -392,23 +478,23 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
 // contiguous run of work items.
 __device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * chunk + blockIdx.x / 8; }
 
-template <int P>
+template <int P, bool BF3>
 __global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
     const int tile = xcd_item(a.chunk);
     if (tile >= a.nblocks) return;
-    stage_tile<P>(a, tile);
+    stage_tile<P, BF3>(a, tile);
 }
 
 // Batched meshes of one order: work item = (job, tile); a job is one mesh's
 // argument record for this stage.
-template <int P>
+template <int P, bool BF3>
 __global__ __launch_bounds__(kBlock) void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs,
                                                              const int2 *__restrict__ items,
                                                              int nitems, int chunk) {
     const int w = xcd_item(chunk);
     if (w >= nitems) return;
     const int2 it = items[w];
-    stage_tile<P>(jobs[it.x], it.y);
+    stage_tile<P, BF3>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -430,6 +516,52 @@ void fill_opsA(const double *Dr, const double *Ds, const double *LIFT, float *ou
                 }
                 out[(mt * S::KS + ks) * 64 + l] = float(v);
             }
+}
+
+// Round to nearest even into BF16 (finite inputs).
+inline unsigned short bf16_rne(float f) {
+    unsigned u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+inline double bf16_value(unsigned short h) {
+    const unsigned u = unsigned(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// BF16x3 A operand: per (output tile, 32-wide k-step) a hi block and a lo
+// block of 64 lanes x 8 BF16 values; lane l, slot i holds row 16 mt + l % 16,
+// column 32 ks + 8 (l / 16) + i; two slots per 32-bit word, low half first.
+template <int P>
+void fill_opsB(const double *Dr, const double *Ds, const double *LIFT, unsigned *out) {
+    using S = MShape<P, true>;
+    constexpr int Np = S::Np, NF3 = S::NF3;
+    for (int mt = 0; mt < S::MT; ++mt)
+        for (int ks = 0; ks < S::KS32; ++ks)
+            for (int l = 0; l < 64; ++l)
+                for (int w = 0; w < 4; ++w) {
+                    unsigned short hv[2], lv[2];
+                    for (int h = 0; h < 2; ++h) {
+                        const int m = 16 * mt + (l & 15), k = 32 * ks + 8 * (l >> 4) + 2 * w + h;
+                        double v = 0.0;
+                        if (m < Np) {
+                            if (k < Np)
+                                v = -Dr[m * Np + k];
+                            else if (k < 2 * Np)
+                                v = -Ds[m * Np + (k - Np)];
+                            else if (k < S::KV)
+                                v = LIFT[m * NF3 + (k - 2 * Np)];
+                        }
+                        hv[h] = bf16_rne(float(v));
+                        lv[h] = bf16_rne(float(v - bf16_value(hv[h])));
+                    }
+                    const int z = mt * S::KS32 + ks;
+                    out[((2 * z) * 64 + l) * 4 + w] = unsigned(hv[0]) | unsigned(hv[1]) << 16;
+                    out[((2 * z + 1) * 64 + l) * 4 + w] = unsigned(lv[0]) | unsigned(lv[1]) << 16;
+                }
 }
 
 template <typename F>
@@ -455,6 +587,20 @@ size_t mfma_opsA_floats(int P) {
 void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out) {
     with_order_m(P, [&](auto PC) {
         fill_opsA<decltype(PC)::value>(Dr, Ds, LIFT, out);
+        return 0;
+    });
+}
+
+size_t mfma_opsB_words(int P) {
+    return with_order_m(P, [](auto PC) {
+        using S = MShape<decltype(PC)::value, true>;
+        return size_t(S::MT) * S::KS32 * 2 * 64 * 4;
+    });
+}
+
+void mfma_fill_opsB(int P, const double *Dr, const double *Ds, const double *LIFT, unsigned *out) {
+    with_order_m(P, [&](auto PC) {
+        fill_opsB<decltype(PC)::value>(Dr, Ds, LIFT, out);
         return 0;
     });
 }
@@ -488,7 +634,7 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
     a.geoA = reinterpret_cast<const float4 *>(m.geoA);
     a.cidx = m.cidx;
     a.geoC = m.geoC;
-    a.opsA = m.opsA;
+    a.opsA = m.bf3 ? reinterpret_cast<const float *>(m.opsB) : m.opsA;
     a.ops = m.ops32;
     a.scal = m.scal;
     a.vmax_in = step.vmax_in;
@@ -518,14 +664,20 @@ int mfma_tiles(const DevMesh &m) {
     });
 }
 
-hipError_t launch_stage_mfma_batch(int P, const void *jobs, const void *items, int nitems, hipStream_t st) {
+hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void *items, int nitems,
+                                   hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const int chunk = (nitems + 7) / 8;
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
-        hipLaunchKernelGGL((k_stage_mfma_batch<PP>), dim3(8 * chunk), dim3(kBlock), 0, st,
-                           static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
-                           chunk);
+        if (bf3)
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true>), dim3(8 * chunk), dim3(kBlock), 0, st,
+                               static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
+                               chunk);
+        else
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false>), dim3(8 * chunk), dim3(kBlock), 0, st,
+                               static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
+                               chunk);
         return hipGetLastError();
     });
 }
@@ -535,7 +687,10 @@ hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void
     MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step);
     return with_order_m(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        hipLaunchKernelGGL((k_stage_mfma<P>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
+        if (m.bf3)
+            hipLaunchKernelGGL((k_stage_mfma<P, true>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_stage_mfma<P, false>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
         return hipGetLastError();
     });
 }

@@ -19,8 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DG_LIBRARY") or os.path.join(HERE, "libdg.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EGEOM, DG_ENONFINITE, DG_EDEVICE, DG_EBUSY = 0, -1, -2, -3, -4, -5, -6
-DG_FP64_PLAIN, DG_FP32 = 0, 2
-PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP32}
+DG_FP64_PLAIN, DG_FP32, DG_FP32_BF16X3 = 0, 2, 3
+PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP32,
+              "bf16x3": DG_FP32_BF16X3}
 
 # Every symbol include/dg.h declares.
 EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
@@ -172,7 +173,7 @@ class Solver:
         self.P = int(P)
         self.Np = n_nodes(self.P)
         self.precision = precision
-        self.dtype = torch.float32 if PRECISIONS[precision] == DG_FP32 else torch.float64
+        self.dtype = torch.float64 if PRECISIONS[precision] == DG_FP64_PLAIN else torch.float32
         self._keep = [np.ascontiguousarray(EToE, dtype=np.int32),
                       np.ascontiguousarray(EToF, dtype=np.int32),
                       np.ascontiguousarray(bc, dtype=np.int8),

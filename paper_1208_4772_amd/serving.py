@@ -59,8 +59,9 @@ def make_requests(n=64, mean_gap=0.05, seed=64, K_range=(2000, 60000), steps_ran
     """The seeded request mix: case in {cylinder, airfoil}, element count
     uniform in K_range, order uniform over P_choices, Mach uniform in
     mach_range, step count uniform in steps_range, exponential arrival gaps
-    of mean ``mean_gap`` seconds.  The airfoil runs with the shock sensor and
-    artificial viscosity unless ``av`` says otherwise."""
+    of mean ``mean_gap`` seconds.  Every request runs with the shock sensor
+    and artificial viscosity (Mach numbers up to 0.85 form shocks on both
+    geometries) unless ``av`` says otherwise."""
     rng = np.random.default_rng(seed)
     t = 0.0
     reqs = []
@@ -82,10 +83,13 @@ def build_case(req: Request):
     """Mesh, node positions and freestream start of a request (host)."""
     rr, ss = dg.reference_nodes(req.P)
     scale = req.K_target / _DEFAULT_K[req.kind]
-    case = meshgen.make_case(req.kind, rr, ss, scale=scale, P=req.P, mach=req.mach, steps=req.steps)
-    if req.av is not None:
-        case.av = req.av
-    req.av = bool(case.av)
+    # cylinders start from the wall-compatible potential flow: the impulsive
+    # start drives the coarse high-order meshes of the mix to rho, p <= 0
+    start = "potential" if req.kind == "cylinder" else "freestream"
+    case = meshgen.make_case(req.kind, rr, ss, scale=scale, P=req.P, mach=req.mach, steps=req.steps,
+                             start=start)
+    case.av = True if req.av is None else bool(req.av)
+    req.av = case.av
     req.case = case
     return case
 

@@ -99,3 +99,26 @@ def test_vortex_state_is_radially_balanced():
     rho, vt, _ = prim(x)
     dp = (prim(x + h)[2] - prim(x - h)[2]) / (2 * h)
     np.testing.assert_allclose(dp, rho * vt ** 2 / r, rtol=1e-6, atol=1e-9)
+
+
+def test_cylinder_potential_start():
+    """Zero normal velocity on the wall, freestream far away, constant
+    total enthalpy (c^2/(gamma-1) + |v|^2/2), and no divergence."""
+    th = np.linspace(0, 2 * np.pi, 37)
+    U = meshgen.cylinder_potential(np.cos(th), np.sin(th), 0.6)
+    rho, u, v = U[0], U[1] / U[0], U[2] / U[0]
+    np.testing.assert_allclose(u * np.cos(th) + v * np.sin(th), 0, atol=1e-14)
+    far = meshgen.cylinder_potential(np.array([1e6]), np.array([3e5]), 0.6)
+    np.testing.assert_allclose(far[:, 0], meshgen.freestream_state(0.6), rtol=1e-9, atol=1e-9)
+    x, y = (a.ravel() for a in np.meshgrid(np.linspace(1.5, 4, 7), np.linspace(-3, 3, 7)))
+    U = meshgen.cylinder_potential(x, y, 0.6)
+    rho, u, v = U[0], U[1] / U[0], U[2] / U[0]
+    p = 0.4 * (U[3] - 0.5 * rho * (u * u + v * v))
+    H = 1.4 * p / rho / 0.4 + 0.5 * (u * u + v * v)
+    np.testing.assert_allclose(H, 1 / 0.4 + 0.18, rtol=1e-13)
+    h = 1e-5
+    div = ((meshgen.cylinder_potential(x + h, y, 0.6)[1] / meshgen.cylinder_potential(x + h, y, 0.6)[0]
+            - meshgen.cylinder_potential(x - h, y, 0.6)[1] / meshgen.cylinder_potential(x - h, y, 0.6)[0])
+           + (meshgen.cylinder_potential(x, y + h, 0.6)[2] / meshgen.cylinder_potential(x, y + h, 0.6)[0]
+              - meshgen.cylinder_potential(x, y - h, 0.6)[2] / meshgen.cylinder_potential(x, y - h, 0.6)[0])) / (2 * h)
+    np.testing.assert_allclose(div, 0, atol=1e-8)

@@ -26,4 +26,4 @@ def test_case_sizes_follow_targets():
     for r in reqs:
         assert 0.7 * r.K_target <= r.case.K <= 1.3 * r.K_target, (r.kind, r.K_target, r.case.K)
         assert r.case.P == r.P and r.case.steps == r.steps
-        assert r.av == (r.kind == "airfoil")
+        assert r.av
