@@ -48,9 +48,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(precision="fp32"):
+    """Hash of the sources of the dominant stage kernel for this precision."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "common.hpp"):
+    files = ("kernels.hip", "common.hpp") if precision == "fp64" else ("stage_mfma.hip", "common.hpp")
+    for f in files:
         with open(os.path.join(ROOT, "paper_1208_4772_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -87,7 +89,7 @@ def load_traffic(workload, precision, launch_bytes):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(precision):
         return None
     return t.get("bytes_per_launch")
 
@@ -122,7 +124,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed LSERK steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="cylinder", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -167,59 +169,46 @@ def main():
     log(f"workload {args.workload}: K={case.K} P={case.P} Np={case.Np} DOF={case.dofs()} "
         f"steps={steps} warmup={args.warmup}")
 
-    def timed_run(precision, nsteps, warmup, kernel_timing):
+    def timed_run(precision, nsteps, warmup):
         sol = dg.Solver.from_case(case, precision, device="cuda:0")
         U0 = sol.state(case.U0)
         U = U0.clone()
         if warmup:
             sol.run(U, warmup)
         U.copy_(U0)
-        sol.set_kernel_timing(kernel_timing)
-        sol.kernel_time()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = sol.run(U, nsteps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        kms, kn = sol.kernel_time()
         ok = bool(torch.isfinite(U).all().item())
         sol.close()
-        return wall, st, kms, kn, ok
+        return wall, st, ok
 
-    def event_pair_overhead_ms(n=200):
-        """Median elapsed time of an empty HIP event pair on this stream: the
-        fixed cost each bracketed launch carries besides the kernel itself."""
-        torch.cuda.synchronize()
-        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                 for _ in range(n)]
-        for a0, a1 in pairs:
-            a0.record()
-            a1.record()
-        torch.cuda.synchronize()
-        return float(np.median([a0.elapsed_time(a1) for a0, a1 in pairs]))
-
-    wall, st, kms, kn, ok = timed_run(args.precision, steps, args.warmup, True)
-    ev_ms = event_pair_overhead_ms()
+    # the timed run: replayed step graphs.  dg_run brackets its steps with a
+    # HIP event pair on the launch stream; inside that region the GPU runs
+    # the five stage launches of every step (plus one CFL launch before the
+    # first step), so region time / stage launches is the stage kernel's
+    # average launch duration, inter-launch gaps included.
+    wall, st, ok = timed_run(args.precision, steps, args.warmup)
     if not ok or st.status != 0:
         raise SystemExit("state became non-finite in the timed run")
     dofs = case.dofs()
     value = dofs * 5 * steps / wall
+    avg_s = st.wall_s / (5 * steps)
     log(f"{args.precision}: {wall * 1e3:.2f} ms for {steps} steps -> {value:.4e} DOF-updates/s "
-        f"(device events {st.wall_s * 1e3:.2f} ms); stage kernel {kn} launches, "
-        f"avg {kms / max(kn, 1) * 1e3:.2f} us")
+        f"(device events {st.wall_s * 1e3:.2f} ms, {avg_s * 1e6:.2f} us per stage launch)")
 
-    sbytes = 4 if args.precision == "fp32" else 8
+    sbytes = 8 if args.precision == "fp64" else 4
     launch_bytes, geo_info = algorithmic_stage_bytes(case, sbytes)
-    raw_avg_s = kms / max(kn, 1) * 1e-3
-    avg_s = max(raw_avg_s - ev_ms * 1e-3, 0.5 * raw_avg_s)
     achieved = launch_bytes / avg_s / 1e9
     traffic = load_traffic(args.workload, args.precision, launch_bytes)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=f"k_stage<{'float' if sbytes == 4 else 'double'},P={case.P}>",
+                    kernel=(f"k_stage<double,{case.P},false>" if args.precision == "fp64" else
+                            f"k_stage_mfma<{case.P},{'true' if args.precision == 'bf16x3' else 'false'}>"),
                     avg_launch_us=round(avg_s * 1e6, 3),
-                    raw_event_avg_us=round(raw_avg_s * 1e6, 3),
-                    event_pair_overhead_us=round(ev_ms * 1e3, 3),
+                    launches=5 * steps,
                     algorithmic_bytes_per_launch=int(launch_bytes))
 
     out = {
@@ -233,17 +222,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "K": case.K, "P": case.P,
                    "dof": dofs, "precision": args.precision,
                    "curved_elements": geo_info["curved"]},
         "roofline": roofline,
     }
-    if not args.no_fp64 and args.precision == "fp32":
-        w64, st64, k64, n64, ok64 = timed_run("fp64", steps, args.warmup, True)
+    if not args.no_fp64 and args.precision != "fp64":
+        w64, st64, ok64 = timed_run("fp64", steps, args.warmup)
         out["fp64_plain"] = dict(value=dofs * 5 * steps / w64, ms_per_step=w64 * 1e3 / steps,
-                                 stage_kernel_avg_us=round(k64 / max(n64, 1) * 1e3, 3),
                                  finite=ok64)
         out["fp32_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 3)
         log(f"fp64 plain: {w64 * 1e3:.2f} ms -> {out['fp64_plain']['value']:.4e} DOF-updates/s")

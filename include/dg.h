@@ -221,8 +221,11 @@ int dg_batch_admit(dg_batch *batch, dg_mesh *mesh, void *U, void *work, int nste
  * *steps_run receives that number.  Enqueues only. */
 int dg_batch_advance(dg_batch *batch, int max_steps, void *stream, int *steps_run);
 
-/* Synchronise the stream and list slots that have finished all their steps
- * and are not yet released (up to max_done ids; *ndone = how many). */
+/* Synchronise the stream and list slots that are done and not yet released
+ * (up to max_done ids; *ndone = how many).  A slot is done when it has run
+ * all its steps, or when its state check has failed (non-finite state,
+ * rho <= 0 or p <= 0): such a slot retires at this poll, and its stats
+ * report DG_ENONFINITE and the steps it ran. */
 int dg_batch_poll(dg_batch *batch, void *stream, int *done_slots, int max_done, int *ndone);
 
 /* Steps done, simulated time, dt range and status of a slot (synchronises). */

@@ -48,9 +48,14 @@ struct dg_mesh {
     int alloc(T **p, size_t count) {
         void *q = nullptr;
         if (count == 0) count = 1;
-        if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        const hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) {
             (void)hipGetLastError();
-            return fail(DG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+            size_t fr = 0, tot = 0;
+            (void)hipMemGetInfo(&fr, &tot);
+            return fail(DG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed (" +
+                                       hipGetErrorString(e) + "; device free " + std::to_string(fr) + " of " +
+                                       std::to_string(tot) + " bytes)");
         }
         allocs.push_back(q);
         owned_bytes += count * sizeof(T);
@@ -960,7 +965,23 @@ int dg_batch_advance(dg_batch *b, int max_steps, void *stream, int *steps_run) {
 
 int dg_batch_poll(dg_batch *b, void *stream, int *done_slots, int max_done, int *ndone) {
     if (!b || !ndone) return fail(DG_EINVAL, "null argument");
-    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // state checks of the running slots: a slot whose state went non-finite
+    // (or rho <= 0, p <= 0) retires now instead of running out its steps
+    std::vector<int> flags(b->slots.size(), 0);
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const Slot &s = b->slots[i];
+        if (s.used && !s.finished)
+            HIP_TRY(hipMemcpyAsync(&flags[i], s.mesh->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        Slot &s = b->slots[i];
+        if (s.used && !s.finished && flags[i]) {
+            s.finished = true;
+            b->dirty = true;
+        }
+    }
     int n = 0;
     for (size_t i = 0; i < b->slots.size(); ++i)
         if (b->slots[i].used && b->slots[i].finished) {

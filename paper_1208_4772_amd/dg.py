@@ -65,6 +65,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1208_4772_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # already loaded (same soname) instead of bringing a second one into
+        # the process, which would not see the device
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i, d = C.c_void_p, C.c_int, C.c_double
         L.dg_last_error.restype = C.c_char_p

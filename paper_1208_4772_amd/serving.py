@@ -44,6 +44,7 @@ class Request:
     status: int = 0
     t_sim: float = math.nan
     final_state: object = None   # host copy of the result when the server keeps states
+    error: str = ""
 
     @property
     def dofs(self):
@@ -128,13 +129,18 @@ class Server:
     """Continuous-batching server over one GPU."""
 
     def __init__(self, hbm_budget_bytes=1 << 30, max_slots=16, precision="fp32", chunk_steps=50,
-                 device="cuda:0", keep_states=False):
+                 device="cuda:0", keep_states=False, verbose=False):
         self.keep_states = bool(keep_states)
+        self.verbose = bool(verbose)
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.precision = precision
         self.chunk_steps = int(chunk_steps)
         self.device = device
+
+    def _log(self, msg):
+        if self.verbose:
+            print(msg, flush=True)
 
     def run(self, requests):
         import torch
@@ -162,7 +168,16 @@ class Server:
                     continue
                 if reserved + est > self.budget:
                     break
-                sol = dg.Solver.from_case(req.case, self.precision, device=self.device)
+                try:
+                    sol = dg.Solver.from_case(req.case, self.precision, device=self.device)
+                except dg.DGError as e:
+                    # a request whose setup fails is reported, not retried
+                    queue.popleft()
+                    req.status = e.code
+                    req.error = str(e)
+                    req.admitted = req.finished = time.perf_counter() - t0
+                    self._log(f"request {req.rid} setup failed: {e}")
+                    continue
                 U = sol.state(req.case.U0)
                 slot = batch.admit(sol, U, req.steps)
                 if slot is None:
@@ -190,6 +205,8 @@ class Server:
                 batch.release(slot)
                 reserved -= est
                 sol.close()
+                self._log(f"request {req.rid} done: status {req.status}, latency {req.latency:.3f} s, "
+                          f"{len(active)} active, {len(queue)} queued")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         batch.close()
@@ -212,7 +229,7 @@ def main(argv=None):
     t = time.perf_counter()
     reqs = make_requests(a.requests, a.mean_gap, a.seed)
     print(f"built {len(reqs)} requests in {time.perf_counter() - t:.1f} s", flush=True)
-    srv = Server(int(a.budget_gib * 2**30), a.max_slots, a.precision, a.chunk_steps)
+    srv = Server(int(a.budget_gib * 2**30), a.max_slots, a.precision, a.chunk_steps, verbose=True)
     rep = srv.run(reqs)
     print(json.dumps(rep.summary()), flush=True)
 

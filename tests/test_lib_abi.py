@@ -92,3 +92,16 @@ def test_setup_rejects_bad_input_before_touching_the_device():
     assert rc == dg.DG_EINVAL and "out of range" in msg
     rc, msg, _ = setup(bc=np.array([[1, 0, 0], [0, 0, 0]], dtype=np.int8))
     assert rc == dg.DG_EINVAL
+
+
+def test_one_hip_runtime_in_process():
+    """Loading the library must not bring a second HIP runtime next to the
+    one torch uses (a second copy does not see the device)."""
+    import subprocess
+    import sys
+    code = ("from paper_1208_4772_amd import dg; dg.lib(); import torch; "
+            "m = open('/proc/self/maps').read().splitlines(); "
+            "print(len({l.split()[-1] for l in m if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
+                         cwd=ROOT)
+    assert out.stdout.strip().splitlines()[-1] == "1"
