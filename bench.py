@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the occupancy-limit launch shape instead of timing the candidates")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (HBM peak probe and "
@@ -169,10 +171,14 @@ def main():
     log(f"workload {args.workload}: K={case.K} P={case.P} Np={case.Np} DOF={case.dofs()} "
         f"steps={steps} warmup={args.warmup}")
 
+    tuned = {}
+
     def timed_run(precision, nsteps, warmup):
         sol = dg.Solver.from_case(case, precision, device="cuda:0")
         U0 = sol.state(case.U0)
         U = U0.clone()
+        if not args.no_autotune:
+            tuned[precision] = sol.autotune(U)
         if warmup:
             sol.run(U, warmup)
         U.copy_(U0)
@@ -209,6 +215,7 @@ def main():
                             f"k_stage_mfma<{case.P},{'true' if args.precision == 'bf16x3' else 'false'}>"),
                     avg_launch_us=round(avg_s * 1e6, 3),
                     launches=5 * steps,
+                    waves_per_block=tuned.get(args.precision, (0, 0.0))[0] or None,
                     algorithmic_bytes_per_launch=int(launch_bytes))
 
     out = {

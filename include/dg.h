@@ -184,6 +184,19 @@ int dg_set_graphs(dg_mesh *mesh, int enable);
  * number of launches, and resets both.  Used by benchmarks to report the
  * dominant kernel's average duration measured inside the timed region. */
 int dg_set_kernel_timing(dg_mesh *mesh, int enable);
+
+/* Autotuner for the workgroup shape of the FP32 matrix-core stage kernel:
+ * elements per workgroup = 2, 4 or 8 wavefronts times the elements one
+ * wavefront holds (floor(64 / Np)).  Times each candidate over a few rhs
+ * evaluations of the device state U [K][4][Np] and keeps the fastest for
+ * this handle (results do not depend on the choice).  work is the handle's
+ * work buffer (its contents between steps are scratch).  *waves_per_block
+ * receives the choice and *stage_us the measured time of one launch (either
+ * may be NULL).  Handles without the matrix-core kernel (FP64, artificial
+ * viscosity) return DG_OK with 0.  Batches keep the default shape (4).
+ * Synchronises the stream.  Errors: DG_EINVAL, DG_EDEVICE. */
+int dg_autotune(dg_mesh *mesh, const void *U, void *work, void *stream, int *waves_per_block,
+                double *stage_us);
 int dg_kernel_time(dg_mesh *mesh, void *stream, double *stage_ms_total, long *stage_launches);
 
 /* Device bytes a handle holds (geometry, operators, scratch) plus one state

@@ -359,9 +359,9 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         SETUP_TRY(hipGetDevice(&dev));
         SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         dm.ncu = ncu > 0 ? ncu : 256;
-        if (const char *e = std::getenv("DG_BLOCKS_PER_CU")) {
-            const int b = std::atoi(e);
-            if (b >= 1 && b <= 16) dm.blocks_per_cu = b;
+        if (const char *e = std::getenv("DG_WAVES_PER_BLOCK")) {
+            const int w = std::atoi(e);
+            if (w == 2 || w == 4 || w == 8) dm.waves_per_block = w;
         }
         SETUP_TRY(hipStreamSynchronize(st));
     }
@@ -638,6 +638,65 @@ int dg_viscosity(dg_mesh *m, const void *U, double *eps, void *stream) {
 int dg_set_kernel_timing(dg_mesh *m, int enable) {
     if (!m) return fail(DG_EINVAL, "mesh is NULL");
     m->timing = enable != 0;
+    return DG_OK;
+}
+
+int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_per_block, double *stage_us) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (int rc = check_ptr(work, "work")) return rc;
+    if (waves_per_block) *waves_per_block = 0;
+    if (stage_us) *stage_us = 0.0;
+    if (!m->dm.fp32 || m->dm.av) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // candidates: workgroups of 2, 4 and 8 wavefronts (2, 4 or 8 times the
+    // elements one wavefront holds), each timed over a few rhs evaluations
+    // of U written into the work buffer's A slot (scratch between steps)
+    static const int kCand[3] = {2, 4, 8};
+    void *out = static_cast<char *>(work) + m->off_A();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int saved = m->dm.waves_per_block;
+    int best = 0;
+    float best_ms = 0.f;
+    constexpr int kReps = 5;
+    int rc = DG_OK;
+    for (int ci = 0; ci < 3 && rc == DG_OK; ++ci) {
+        const int c = kCand[ci];
+        m->dm.waves_per_block = c;
+        hipError_t e = launch_stage_mfma(m->dm, U, nullptr, nullptr, out, 0, MfmaStep(), st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r)
+            e = launch_stage_mfma(m->dm, U, nullptr, nullptr, out, 0, MfmaStep(), st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(DG_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+        }
+        if (best == 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DG_OK) {
+        m->dm.waves_per_block = saved;
+        return rc;
+    }
+    m->dm.waves_per_block = best;
+    // captured step graphs hold the old launch shape
+    if (m->graph_exec) {
+        (void)hipGraphExecDestroy(m->graph_exec);
+        m->graph_exec = nullptr;
+        m->graph_U = m->graph_work = nullptr;
+    }
+    if (waves_per_block) *waves_per_block = best;
+    if (stage_us) *stage_us = 1e3 * best_ms / kReps;
     return DG_OK;
 }
 

@@ -45,7 +45,7 @@ struct DevMesh {
     const unsigned *opsB = nullptr; // BF16x3 A operand table (hi and lo splits)
     int Kc = 0;
     int ncu = 256;                  // compute units of the device
-    int blocks_per_cu = 4;          // persistent blocks per CU (matrix-core kernel)
+    int waves_per_block = 0;        // stage-kernel workgroup shape: 2, 4 or 8 wavefronts (0: default 4)
     unsigned long long *vmax = nullptr;   // [2] CFL-bound slots (FP64 bit patterns)
     // device scalars and reduction scratch
     double *scal = nullptr;   // [S_NSCAL]
@@ -105,7 +105,7 @@ size_t mfma_opsA_floats(int P);
 void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out);
 size_t mfma_opsB_words(int P);
 void mfma_fill_opsB(int P, const double *Dr, const double *Ds, const double *LIFT, unsigned *out);
-int mfma_elements_per_block(int P);
+int mfma_elements_per_block(int P, int waves);
 // setup: flags[k] = 1 if element k's metric terms, normals and Fscale are
 // constant to 1e-10 relative (a straight element)
 hipError_t launch_affine_flags(const DevMesh &m, int *flags, hipStream_t st);

@@ -42,12 +42,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 256;
+constexpr int kWaves = 4;   // default waves per workgroup
 constexpr int kCurvedBit = 1 << 12;   // in the packed face-info word
 
 // BF3: the product runs as three BF16 products (v_mfma_f32_16x16x32_bf16)
-// of hi/lo splits, K padded to multiples of 32.
-template <int P, bool BF3 = false>
+// of hi/lo splits, K padded to multiples of 32.  W: wavefronts per
+// workgroup (the elements per workgroup are W times those of a wavefront).
+template <int P, bool BF3 = false, int W = kWaves>
 struct MShape {
     static constexpr int Np = (P + 1) * (P + 2) / 2;
     static constexpr int Nfp = P + 1;
@@ -58,11 +59,12 @@ struct MShape {
     static constexpr int KP = BF3 ? 32 * KS32 : 4 * KS;  // padded contraction length
     static constexpr int MT = (Np + 15) / 16;   // 16-row output tiles
     static constexpr int EW = 64 / Np;          // elements per wavefront (pointwise phase)
-    static constexpr int EB = 4 * EW;           // elements per block
-    static constexpr int NT = EB / 4;           // 16-column groups per block
-    static constexpr int TF = EB * 4 * Np;      // state floats per block (<= 1024)
-    static constexpr int TPT = (EB * NF3 + 255) / 256;  // face-node tasks per thread
-    static_assert(TF <= 4 * kBlock, "one float4 per thread covers the tile");
+    static constexpr int NTH = 64 * W;          // threads per block
+    static constexpr int EB = W * EW;           // elements per block
+    static constexpr int NT = (EB + 3) / 4;     // 16-column groups per block
+    static constexpr int TF = EB * 4 * Np;      // state floats per block
+    static constexpr int TPT = (EB * NF3 + NTH - 1) / NTH;  // face-node tasks per thread
+    static_assert(TF <= 4 * NTH, "one float4 per thread covers the tile");
     static_assert(16 * Np <= 16 * KP, "a column group's result fits in its B block");
 };
 
@@ -100,12 +102,12 @@ __device__ __forceinline__ int face_node_sel(int f, int j) {
 // Lax-Friedrichs face term of one face-node task, scaled by Fscale, into the
 // B operand.  CURVED: the tile holds curved elements, whose normals and
 // Fscale are per face node.
-template <int P, bool BF3, bool CURVED>
+template <int P, bool BF3, int W, bool CURVED>
 __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, const int el, const int q,
                                           const float (&upn)[4], const float *sU, const float (*sG)[16],
-                                          const int4 *sC, const int *sFN, const float (*sPrim)[4],
+                                          const int4 *sC, const int *sFN, const float2 *sPrim,
                                           float *sBflat) {
-    using S = MShape<P, BF3>;
+    using S = MShape<P, BF3, W>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KP = S::KP;
     const int f = q / Nfp;
     const int vm = sFN[q];
@@ -132,10 +134,10 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
         ghost_state(a.g, code, um, nx, ny, a.ff, up);
     }
     // n.F(U-) and its wave speed from the pointwise phase's primitives
-    const f32x4 pm = *reinterpret_cast<const f32x4 *>(sPrim[el * Np + vm]);
-    const float vnm = (um[1] * nx + um[2] * ny) * pm[0];
-    const float fm[4] = {um[0] * vnm, um[1] * vnm + pm[1] * nx, um[2] * vnm + pm[1] * ny, (um[3] + pm[1]) * vnm};
-    const float lm = fabsf(vnm) + pm[2];
+    const float2 pm = sPrim[el * Np + vm];
+    const float vnm = (um[1] * nx + um[2] * ny) * pm.x;
+    const float fm[4] = {um[0] * vnm, um[1] * vnm + pm.y * nx, um[2] * vnm + pm.y * ny, (um[3] + pm.y) * vnm};
+    const float lm = fabsf(vnm) + fsqrt(a.g * pm.y * pm.x);
     float fp[4], lp;
     normal_flux(a.g, up, nx, ny, fp, lp);
     const float lam = lm > lp ? lm : lp;
@@ -148,9 +150,10 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
 // One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
 // arguments (single mesh) or in a device job table (batched meshes); its
 // fields are uniform across the block.
-template <int P, bool BF3>
+template <int P, bool BF3, int W>
 __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
-    using S = MShape<P, BF3>;
+    using S = MShape<P, BF3, W>;
+    constexpr int NTH = S::NTH;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KS32 = S::KS32, KP = S::KP, MT = S::MT;
     constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF, TPT = S::TPT;
 
@@ -179,9 +182,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     __shared__ float sG[EB][16];
     __shared__ int4 sC[EB];
     __shared__ int sAny;
-    __shared__ float sRed[kBlock / 64];
+    __shared__ float sRed[W];
     __shared__ int sFN[NF3];              // face node ids, face-major, counter-clockwise
-    __shared__ float sPrim[EB * Np][4];   // 1/rho, p, sound speed, unused (pointwise phase)
+    __shared__ float2 sPrim[EB * Np];     // 1/rho, p (pointwise phase)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -199,7 +202,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     int4 tconn[TPT];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const int task = min(tid + t * kBlock, ntask - 1);
+        const int task = min(tid + t * NTH, ntask - 1);
         tconn[t] = a.conn[k0 + task / NF3];
     }
     const bool flat_ok = 4 * tid < nflt;
@@ -209,7 +212,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     float upn[TPT][4];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const int task = min(tid + t * kBlock, ntask - 1);
+        const int task = min(tid + t * NTH, ntask - 1);
         const int q = task % NF3, f = q / Nfp, j = q - f * Nfp;
         const int4 cv = tconn[t];
         const bool inner = face_bc(cv.w, f) == BC_INTERIOR;
@@ -226,7 +229,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     if (tid < NF3) sFN[tid] = face_node_sel<P>(tid / Nfp, tid % Nfp);
     if constexpr (KP > S::KV) {
         constexpr int PADN = (KP - S::KV) * 16;
-        for (int z = tid; z < NT * PADN; z += kBlock) {
+        for (int z = tid; z < NT * PADN; z += NTH) {
             const int t = z / PADN, rem = z - t * PADN;
             sB[t][S::KV + rem / 16][rem % 16] = 0.f;
         }
@@ -250,7 +253,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         const float p = pressure_ir(a.g, u, ir);
         const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
         const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
-        *reinterpret_cast<f32x4 *>(sPrim[eln * Np + in]) = f32x4{ir, p, fsqrt(a.g * p * ir), 0.f};
+        sPrim[eln * Np + in] = make_float2(ir, p);
         const int t = eln >> 2, col = (eln & 3) * 4;
         f32x4 f, gg;
         curved_lane = sC[eln].w & kCurvedBit;
@@ -278,13 +281,13 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     // ---- Lax-Friedrichs flux at the face nodes
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const int task = tid + t * kBlock;
+        const int task = tid + t * NTH;
         if (task < ntask) {
             const int el = task / NF3, q = task - el * NF3;
             if (any_curved)
-                face_task<P, BF3, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
+                face_task<P, BF3, W, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
             else
-                face_task<P, BF3, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
+                face_task<P, BF3, W, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
         }
     }
     __syncthreads();
@@ -328,7 +331,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     // ---- the contraction on the matrix cores: wave w takes column groups
     // w, w+4, ...; result row = node, column = 4 * element + field.  The
     // wavefront writes the result over its own (fully consumed) B block.
-    for (int t = wave; t < NT; t += 4) {
+    for (int t = wave; t < NT; t += W) {
         f32x4 acc[MT], acc2[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -467,7 +470,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         __syncthreads();
         if (tid == 0) {
             float m = sRed[0];
-            for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sRed[w]);
+            for (int w = 1; w < W; ++w) m = fmaxf(m, sRed[w]);
             // a NaN speed leaves m unordered; the flag above reports it
             atomicMax(a.vmax_out, (unsigned long long)__double_as_longlong(double(m)));
         }
@@ -478,23 +481,39 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
 // contiguous run of work items.
 __device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * chunk + blockIdx.x / 8; }
 
-template <int P, bool BF3>
-__global__ __launch_bounds__(kBlock) void k_stage_mfma(MfmaArgs a) {
+// Occupancy request: as many resident waves per SIMD as the LDS allows (at
+// most 8), which caps the registers per lane at 512 / waves; the kernel
+// hides its memory latency with resident waves.
+template <int P, bool BF3, int W>
+constexpr int waves_per_simd() {
+    using S = MShape<P, BF3, W>;
+    constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + S::EB * 16 + S::EB * S::Np * 8 + 256;
+    constexpr int blocks = (160 * 1024) / lds;      // resident blocks per CU by LDS
+    constexpr int waves = blocks * W / 4;           // per SIMD
+    // the BF16x3 product holds its hi/lo operand fragments in registers:
+    // at most 6 waves (85 registers) so that nothing spills
+    constexpr int cap = BF3 ? 6 : 8;
+    return waves >= cap ? cap : (waves < 1 ? 1 : waves);
+}
+
+template <int P, bool BF3, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W>())))
+void k_stage_mfma(MfmaArgs a) {
     const int tile = xcd_item(a.chunk);
     if (tile >= a.nblocks) return;
-    stage_tile<P, BF3>(a, tile);
+    stage_tile<P, BF3, W>(a, tile);
 }
 
 // Batched meshes of one order: work item = (job, tile); a job is one mesh's
 // argument record for this stage.
-template <int P, bool BF3>
-__global__ __launch_bounds__(kBlock) void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs,
-                                                             const int2 *__restrict__ items,
-                                                             int nitems, int chunk) {
+template <int P, bool BF3, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W>())))
+void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restrict__ items, int nitems,
+                        int chunk) {
     const int w = xcd_item(chunk);
     if (w >= nitems) return;
     const int2 it = items[w];
-    stage_tile<P, BF3>(jobs[it.x], it.y);
+    stage_tile<P, BF3, W>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -605,14 +624,28 @@ void mfma_fill_opsB(int P, const double *Dr, const double *Ds, const double *LIF
     });
 }
 
-int mfma_elements_per_block(int P) {
-    return with_order_m(P, [](auto PC) { return MShape<decltype(PC)::value>::EB; });
+// Dispatch on the waves per workgroup (2, 4 or 8; 0 = the default).
+template <typename F>
+auto with_waves(int w, F &&f) {
+    switch (w) {
+        case 2: return f(std::integral_constant<int, 2>());
+        case 8: return f(std::integral_constant<int, 8>());
+        default: return f(std::integral_constant<int, kWaves>());
+    }
+}
+
+int mfma_elements_per_block(int P, int waves) {
+    return with_order_m(P, [&](auto PC) {
+        return with_waves(waves, [&](auto WC) {
+            return MShape<decltype(PC)::value, false, decltype(WC)::value>::EB;
+        });
+    });
 }
 
 int mfma_curved_bit() { return kCurvedBit; }
 
 static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                          const MfmaStep &step) {
+                          const MfmaStep &step, int waves) {
     MfmaArgs a;
     a.K = m.K;
     a.stage = stage;
@@ -640,28 +673,24 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
     a.vmax_in = step.vmax_in;
     a.vmax_out = step.vmax_out;
     a.flag = m.flag;
-    with_order_m(m.P, [&](auto PC) {
-        using S = MShape<decltype(PC)::value>;
-        a.nblocks = (m.K + S::EB - 1) / S::EB;
-        a.chunk = (a.nblocks + 7) / 8;
-        return 0;
-    });
+    const int eb = mfma_elements_per_block(m.P, waves);
+    a.nblocks = (m.K + eb - 1) / eb;
+    a.chunk = (a.nblocks + 7) / 8;
     return a;
 }
 
 size_t mfma_args_bytes() { return sizeof(MfmaArgs); }
 
+// Batches use the default workgroup shape.
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
                     void *out) {
-    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step);
+    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, kWaves);
     std::memcpy(out, &a, sizeof(a));
 }
 
 int mfma_tiles(const DevMesh &m) {
-    return with_order_m(m.P, [&](auto PC) {
-        using S = MShape<decltype(PC)::value>;
-        return (m.K + S::EB - 1) / S::EB;
-    });
+    const int eb = mfma_elements_per_block(m.P, kWaves);
+    return (m.K + eb - 1) / eb;
 }
 
 hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void *items, int nitems,
@@ -671,27 +700,31 @@ hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
         if (bf3)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true>), dim3(8 * chunk), dim3(kBlock), 0, st,
-                               static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
-                               chunk);
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, kWaves>), dim3(8 * chunk), dim3(64 * kWaves), 0,
+                               st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
+                               nitems, chunk);
         else
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false>), dim3(8 * chunk), dim3(kBlock), 0, st,
-                               static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items), nitems,
-                               chunk);
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, kWaves>), dim3(8 * chunk), dim3(64 * kWaves), 0,
+                               st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
+                               nitems, chunk);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
                              int stage, const MfmaStep &step, hipStream_t st) {
-    MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step);
+    const int waves = m.waves_per_block ? m.waves_per_block : kWaves;
+    MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step, waves);
     return with_order_m(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        if (m.bf3)
-            hipLaunchKernelGGL((k_stage_mfma<P, true>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_stage_mfma<P, false>), dim3(8 * a.chunk), dim3(kBlock), 0, st, a);
-        return hipGetLastError();
+        return with_waves(waves, [&](auto WC) {
+            constexpr int W = decltype(WC)::value;
+            if (m.bf3)
+                hipLaunchKernelGGL((k_stage_mfma<P, true, W>), dim3(8 * a.chunk), dim3(64 * W), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_stage_mfma<P, false, W>), dim3(8 * a.chunk), dim3(64 * W), 0, st, a);
+            return hipGetLastError();
+        });
     });
 }
 

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP3
 EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_reference_operators", "dg_mesh_setup", "dg_mesh_destroy", "dg_buffer_bytes",
            "dg_rhs", "dg_step", "dg_run", "dg_totals", "dg_residual", "dg_viscosity",
-           "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_mesh_footprint",
+           "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_autotune", "dg_mesh_footprint",
            "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
            "dg_status")
@@ -99,6 +99,7 @@ def lib():
         L.dg_batch_slot_stats.argtypes = [vp, i, vp, C.POINTER(RunStats)]
         L.dg_batch_release.argtypes = [vp, i]
         L.dg_kernel_time.argtypes = [vp, vp, C.POINTER(d), C.POINTER(C.c_long)]
+        L.dg_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(i), C.POINTER(d)]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or i
         _lib = L
@@ -288,6 +289,16 @@ class Solver:
         _check(lib().dg_viscosity(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(eps.data_ptr()),
                                   _stream_handle(stream)))
         return eps
+
+    def autotune(self, U, stream=None):
+        """Pick the stage kernel's workgroup shape (2, 4 or 8 wavefronts) by
+        timing (matrix-core path only); returns (waves_per_block, us per
+        launch)."""
+        self._check_state(U)
+        b, us = C.c_int(0), C.c_double(0.0)
+        _check(lib().dg_autotune(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                                 _stream_handle(stream), C.byref(b), C.byref(us)))
+        return b.value, us.value
 
     def set_graphs(self, enable=True):
         _check(lib().dg_set_graphs(self._h, 1 if enable else 0))
