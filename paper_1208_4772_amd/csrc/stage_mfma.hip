@@ -340,10 +340,17 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         }
         if constexpr (!BF3) {
             // A operand fragments straight from global memory (the same few
-            // KB for every block, so they stay in the caches)
-            float av[MT * KS];
+            // KB for every block, so they stay in the caches), four per lane
+            // per 16-byte load
+            constexpr int NZ = MT * KS, NG4 = (NZ + 3) / 4;
+            float av[4 * NG4];
+            const f32x4 *ga = reinterpret_cast<const f32x4 *>(a.opsA);
 #pragma unroll
-            for (int z = 0; z < MT * KS; ++z) av[z] = a.opsA[z * 64 + lane];
+            for (int g = 0; g < NG4; ++g) {
+                const f32x4 v = ga[g * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) av[4 * g + j] = v[j];
+            }
             // two independent accumulation chains per output tile (even and
             // odd k-steps) halve the dependent-MFMA latency
 #pragma unroll
@@ -533,7 +540,9 @@ void fill_opsA(const double *Dr, const double *Ds, const double *LIFT, float *ou
                     else if (k < S::KV)
                         v = LIFT[m * NF3 + (k - 2 * Np)];
                 }
-                out[(mt * S::KS + ks) * 64 + l] = float(v);
+                // lane l's fragments z = mt KS + ks, four per 16-byte group
+                const int z = mt * S::KS + ks;
+                out[((z / 4) * 64 + l) * 4 + z % 4] = float(v);
             }
 }
 
@@ -599,7 +608,7 @@ auto with_order_m(int P, F &&f) {
 size_t mfma_opsA_floats(int P) {
     return with_order_m(P, [](auto PC) {
         using S = MShape<decltype(PC)::value>;
-        return size_t(S::MT) * S::KS * 64;
+        return size_t((S::MT * S::KS + 3) / 4) * 4 * 64;
     });
 }
 
