@@ -105,8 +105,7 @@ __device__ __forceinline__ int face_node_sel(int f, int j) {
 template <int P, bool BF3, int W, bool CURVED>
 __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, const int el, const int q,
                                           const float (&upn)[4], const float *sU, const float (*sG)[16],
-                                          const int4 *sC, const int *sFN, const float2 *sPrim,
-                                          float *sBflat) {
+                                          const int4 *sC, const int *sFN, float *sBflat) {
     using S = MShape<P, BF3, W>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KP = S::KP;
     const int f = q / Nfp;
@@ -133,12 +132,9 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
     } else {
         ghost_state(a.g, code, um, nx, ny, a.ff, up);
     }
-    // n.F(U-) and its wave speed from the pointwise phase's primitives
-    const float2 pm = sPrim[el * Np + vm];
-    const float vnm = (um[1] * nx + um[2] * ny) * pm.x;
-    const float fm[4] = {um[0] * vnm, um[1] * vnm + pm.y * nx, um[2] * vnm + pm.y * ny, (um[3] + pm.y) * vnm};
-    const float lm = fabsf(vnm) + fsqrt(a.g * pm.y * pm.x);
-    float fp[4], lp;
+    // local Lax-Friedrichs: n.F(U-) - F* = (n.F(U-) - n.F(U+)) / 2 + lam (U+ - U-) / 2
+    float fm[4], fp[4], lm, lp;
+    normal_flux(a.g, um, nx, ny, fm, lm);
     normal_flux(a.g, up, nx, ny, fp, lp);
     const float lam = lm > lp ? lm : lp;
 #pragma unroll
@@ -181,10 +177,8 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     __shared__ float sB[NT][KP][16];    // B operand; afterwards the result of that column group
     __shared__ float sG[EB][16];
     __shared__ int4 sC[EB];
-    __shared__ int sAny;
     __shared__ float sRed[W];
     __shared__ int sFN[NF3];              // face node ids, face-major, counter-clockwise
-    __shared__ float2 sPrim[EB * Np];     // 1/rho, p (pointwise phase)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -225,7 +219,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     f32x4 r4 = {0, 0, 0, 0};
     if (a.mode && a.stage > 0) r4 = *reinterpret_cast<const f32x4 *>(a.R + base + (flat_ok ? 4 * tid : 0));
 
-    if (tid == 0) sAny = 0;
     if (tid < NF3) sFN[tid] = face_node_sel<P>(tid / Nfp, tid % Nfp);
     if constexpr (KP > S::KV) {
         constexpr int PADN = (KP - S::KV) * 16;
@@ -237,7 +230,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     if (tid < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid] = g4;
     if (tid < nel) sC[tid] = c4;
     if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
-    __syncthreads();
+    // one barrier for the tile in LDS, which also tells whether it holds a
+    // curved element
+    const bool any_curved = __syncthreads_or(tid < nel && (c4.w & kCurvedBit));
 
     // ---- pointwise fluxes (lane = element * Np + node within the wavefront)
     const int le = lane / Np, in = lane - le * Np;
@@ -253,7 +248,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         const float p = pressure_ir(a.g, u, ir);
         const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
         const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
-        sPrim[eln * Np + in] = make_float2(ir, p);
         const int t = eln >> 2, col = (eln & 3) * 4;
         f32x4 f, gg;
         curved_lane = sC[eln].w & kCurvedBit;
@@ -270,13 +264,12 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
                 f[c] = F[c];
                 gg[c] = G[c];
             }
-            sAny = 1;
         }
         *reinterpret_cast<f32x4 *>(&sB[t][in][col]) = f;
         *reinterpret_cast<f32x4 *>(&sB[t][Np + in][col]) = gg;
     }
-    __syncthreads();
-    const bool any_curved = sAny;
+    // no barrier: the face phase reads only the tile's state, geometry and
+    // connectivity, and writes other rows of the B operand than the fluxes
 
     // ---- Lax-Friedrichs flux at the face nodes
 #pragma unroll
@@ -285,9 +278,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         if (task < ntask) {
             const int el = task / NF3, q = task - el * NF3;
             if (any_curved)
-                face_task<P, BF3, W, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
+                face_task<P, BF3, W, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
             else
-                face_task<P, BF3, W, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, sPrim, &sB[0][0][0]);
+                face_task<P, BF3, W, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
         }
     }
     __syncthreads();
@@ -494,7 +487,7 @@ __device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * c
 template <int P, bool BF3, int W>
 constexpr int waves_per_simd() {
     using S = MShape<P, BF3, W>;
-    constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + S::EB * 16 + S::EB * S::Np * 8 + 256;
+    constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + S::EB * 16 + 256;
     constexpr int blocks = (160 * 1024) / lds;      // resident blocks per CU by LDS
     constexpr int waves = blocks * W / 4;           // per SIMD
     // the BF16x3 product holds its hi/lo operand fragments in registers:
