@@ -187,13 +187,14 @@ int dg_set_kernel_timing(dg_mesh *mesh, int enable);
 
 /* Autotuner for the workgroup shape of the FP32 matrix-core stage kernel:
  * elements per workgroup = 2, 4 or 8 wavefronts times the elements one
- * wavefront holds (floor(64 / Np)).  Times each candidate over a few rhs
- * evaluations of the device state U [K][4][Np] and keeps the fastest for
- * this handle (results do not depend on the choice).  work is the handle's
- * work buffer (its contents between steps are scratch).  *waves_per_block
+ * wavefront holds (floor(64 / Np)).  Times each candidate over Runge-Kutta
+ * stage evaluations of the device state U [K][4][Np] (written into the work
+ * buffer, whose contents between steps are scratch; U is only read) and
+ * keeps the fastest for this handle (results do not depend on the choice).  *waves_per_block
  * receives the choice and *stage_us the measured time of one launch (either
  * may be NULL).  Handles without the matrix-core kernel (FP64, artificial
- * viscosity) return DG_OK with 0.  Batches keep the default shape (4).
+ * viscosity) return DG_OK with 0.  Batches keep the default shape (4
+ * wavefronts).
  * Synchronises the stream.  Errors: DG_EINVAL, DG_EDEVICE. */
 int dg_autotune(dg_mesh *mesh, const void *U, void *work, void *stream, int *waves_per_block,
                 double *stage_us);

@@ -353,7 +353,7 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         dm.opsA = opsA_d;
         dm.Kc = Kc;
         unsigned long long *vmax_d;
-        if ((rc = m->alloc(&vmax_d, 2))) return cleanup(rc);
+        if ((rc = m->alloc(&vmax_d, 2 * kVmaxSlots))) return cleanup(rc);
         dm.vmax = vmax_d;
         int dev = 0, ncu = 0;
         SETUP_TRY(hipGetDevice(&dev));
@@ -447,12 +447,12 @@ static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st,
             ms.dt_fixed = dt;
             if (s == 0) {
                 ms.cfl_mode = 1;
-                ms.vmax_in = m->dm.vmax + fused_parity;
-                ms.vmax_out = m->dm.vmax + (1 - fused_parity);
+                ms.vmax_in = m->dm.vmax + fused_parity * kVmaxSlots;
+                ms.vmax_out = m->dm.vmax + (1 - fused_parity) * kVmaxSlots;
             }
             if (s == 4) {
                 ms.cfl_accum = 1;
-                ms.vmax_out = m->dm.vmax + (1 - fused_parity);
+                ms.vmax_out = m->dm.vmax + (1 - fused_parity) * kVmaxSlots;
             }
             HIP_TRY(m->time_begin(st));
             HIP_TRY(launch_stage_mfma(m->dm, in[s], out[s], R, nullptr, s, ms, st));
@@ -650,38 +650,57 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
     if (!m->dm.fp32 || m->dm.av) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
     hipStream_t st = static_cast<hipStream_t>(stream);
     // candidates: workgroups of 2, 4 and 8 wavefronts (2, 4 or 8 times the
-    // elements one wavefront holds), each timed over a few rhs evaluations
-    // of U written into the work buffer's A slot (scratch between steps)
+    // elements one wavefront holds), each timed over the five Runge-Kutta
+    // stages of a step as a run executes them (ping-pong buffers), reading
+    // U and writing only the work buffer's A, B and R slots (scratch between
+    // steps: a step's first stage overwrites them without reading them)
     static const int kCand[3] = {2, 4, 8};
-    void *out = static_cast<char *>(work) + m->off_A();
+    char *w = static_cast<char *>(work);
+    void *A = w + m->off_A(), *B = w + m->off_B(), *R = w + m->off_R();
+    const void *in5[5] = {U, A, B, A, B};
+    void *out5[5] = {A, B, A, B, A};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int saved = m->dm.waves_per_block;
-    int best = 0;
-    float best_ms = 0.f;
-    constexpr int kReps = 5;
     int rc = DG_OK;
-    for (int ci = 0; ci < 3 && rc == DG_OK; ++ci) {
-        const int c = kCand[ci];
+    // time `reps` launches of candidate c, cycling through the five stages
+    // (ms per launch)
+    auto time_one = [&](int c, int reps, float *ms_per) -> hipError_t {
         m->dm.waves_per_block = c;
-        hipError_t e = launch_stage_mfma(m->dm, U, nullptr, nullptr, out, 0, MfmaStep(), st);
+        hipError_t e = launch_stage_mfma(m->dm, in5[0], out5[0], R, nullptr, 0, MfmaStep(), st);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < kReps && e == hipSuccess; ++r)
-            e = launch_stage_mfma(m->dm, U, nullptr, nullptr, out, 0, MfmaStep(), st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_stage_mfma(m->dm, in5[r % 5], out5[r % 5], R, nullptr, r % 5, MfmaStep(), st);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            rc = fail(DG_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
-            break;
+        *ms_per = ms / reps;
+        return e;
+    };
+    // size the sample to about 2 ms per candidate and round, then take the
+    // best of two interleaved rounds so that a hiccup does not decide
+    float probe = 0.f;
+    hipError_t e = time_one(4, 2, &probe);
+    int reps = probe > 0.f ? int(2.0f / probe) : 50;
+    reps = reps < 5 ? 5 : (reps > 200 ? 200 : reps);
+    reps = (reps + 4) / 5 * 5;   // whole steps
+    float best_of[3] = {0.f, 0.f, 0.f};
+    for (int round = 0; round < 2 && e == hipSuccess; ++round)
+        for (int ci = 0; ci < 3 && e == hipSuccess; ++ci) {
+            float ms = 0.f;
+            e = time_one(kCand[ci], reps, &ms);
+            if (round == 0 || ms < best_of[ci]) best_of[ci] = ms;
         }
-        if (best == 0 || ms < best_ms) {
-            best = c;
-            best_ms = ms;
+    if (e != hipSuccess) rc = fail(DG_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    int best = 0;
+    float best_ms = 0.f;
+    for (int ci = 0; ci < 3; ++ci)
+        if (best == 0 || best_of[ci] < best_ms) {
+            best = kCand[ci];
+            best_ms = best_of[ci];
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != DG_OK) {
@@ -696,7 +715,7 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
         m->graph_U = m->graph_work = nullptr;
     }
     if (waves_per_block) *waves_per_block = best;
-    if (stage_us) *stage_us = 1e3 * best_ms / kReps;
+    if (stage_us) *stage_us = 1e3 * best_ms;
     return DG_OK;
 }
 
@@ -845,12 +864,12 @@ int rebuild(dg_batch *b, hipStream_t st) {
                     MfmaStep ms;
                     if (st5 == 0) {
                         ms.cfl_mode = 1;
-                        ms.vmax_in = m->dm.vmax + par;
-                        ms.vmax_out = m->dm.vmax + (1 - par);
+                        ms.vmax_in = m->dm.vmax + par * kVmaxSlots;
+                        ms.vmax_out = m->dm.vmax + (1 - par) * kVmaxSlots;
                     }
                     if (st5 == 4) {
                         ms.cfl_accum = 1;
-                        ms.vmax_out = m->dm.vmax + (1 - par);
+                        ms.vmax_out = m->dm.vmax + (1 - par) * kVmaxSlots;
                     }
                     mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms,
                                    jobs.data() + ((ps * 5 + st5) * nj + j) * rec);

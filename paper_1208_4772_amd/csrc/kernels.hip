@@ -572,7 +572,9 @@ __global__ __launch_bounds__(kBlock) void k_cfl_finish_vmax(int n, const double 
     double v = 0.0;
     for (int b = threadIdx.x; b < n; b += kBlock) v = v > partial[b] ? v : partial[b];
     const double vmax = block_reduce(v, sh, MaxOp());
-    if (threadIdx.x == 0) *slot = (unsigned long long)__double_as_longlong(vmax);
+    // the bound in the first slot, zeros in the others
+    if (threadIdx.x < kVmaxSlots)
+        slot[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)__double_as_longlong(vmax) : 0ull;
 }
 
 template <typename T, int P>

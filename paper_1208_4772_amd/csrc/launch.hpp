@@ -6,6 +6,11 @@
 
 namespace dg {
 
+// The fused CFL bound is reduced into this many slots per parity (workgroup
+// b uses slot b % kVmaxSlots), so that its atomics do not all hit one
+// address; the next step's first stage takes the maximum of the slots.
+constexpr int kVmaxSlots = 64;
+
 // Slots of the per-mesh FP64 device scalars.
 enum Scalar {
     S_DT = 0,       // step of the current/last step
@@ -45,8 +50,8 @@ struct DevMesh {
     const unsigned *opsB = nullptr; // BF16x3 A operand table (hi and lo splits)
     int Kc = 0;
     int ncu = 256;                  // compute units of the device
-    int waves_per_block = 0;        // stage-kernel workgroup shape: 2, 4 or 8 wavefronts (0: default 4)
-    unsigned long long *vmax = nullptr;   // [2] CFL-bound slots (FP64 bit patterns)
+    int waves_per_block = 0;        // stage-kernel workgroup shape: 2, 4 or 8 wavefronts (0: the order's default)
+    unsigned long long *vmax = nullptr;   // [2][kVmaxSlots] CFL-bound slots (FP64 bit patterns)
     // device scalars and reduction scratch
     double *scal = nullptr;   // [S_NSCAL]
     int *flag = nullptr;      // non-finite / non-positive state flag

@@ -42,7 +42,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;   // default waves per workgroup
+constexpr int kWaves = 4;   // default waves per workgroup (the autotuner may pick 2 or 8)
+constexpr int default_waves(int) { return kWaves; }
 constexpr int kCurvedBit = 1 << 12;   // in the packed face-info word
 
 // BF3: the product runs as three BF16 products (v_mfma_f32_16x16x32_bf16)
@@ -156,15 +157,24 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     // ---- time step of this stage
     double dtd = 0.0;
     if (a.cfl_mode) {
-        const double vmax = __longlong_as_double((long long)*a.vmax_in);
+        // the bound is the maximum over the slots (non-negative doubles order
+        // like their bit patterns); every wavefront reduces them itself
+        unsigned long long vb = a.vmax_in[threadIdx.x & (kVmaxSlots - 1)];
+        for (int off = kVmaxSlots / 2; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(vb, off);
+            vb = o > vb ? o : vb;
+        }
+        const double vmax = __longlong_as_double((long long)vb);
         dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * (1.0 / vmax);
-        if (tile == 0 && threadIdx.x == 0) {
-            a.scal[S_DT] = dtd;
-            a.scal[S_T] += dtd;
-            a.scal[S_DTMIN] = dtd < a.scal[S_DTMIN] ? dtd : a.scal[S_DTMIN];
-            a.scal[S_DTMAX] = dtd > a.scal[S_DTMAX] ? dtd : a.scal[S_DTMAX];
-            a.scal[S_STEPS] += 1.0;
-            *a.vmax_out = 0ull;
+        if (tile == 0 && threadIdx.x < kVmaxSlots) {
+            if (threadIdx.x == 0) {
+                a.scal[S_DT] = dtd;
+                a.scal[S_T] += dtd;
+                a.scal[S_DTMIN] = dtd < a.scal[S_DTMIN] ? dtd : a.scal[S_DTMIN];
+                a.scal[S_DTMAX] = dtd > a.scal[S_DTMAX] ? dtd : a.scal[S_DTMAX];
+                a.scal[S_STEPS] += 1.0;
+            }
+            a.vmax_out[threadIdx.x] = 0ull;
         }
     } else if (a.mode) {
         dtd = a.scal[S_DT];
@@ -472,7 +482,8 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             float m = sRed[0];
             for (int w = 1; w < W; ++w) m = fmaxf(m, sRed[w]);
             // a NaN speed leaves m unordered; the flag above reports it
-            atomicMax(a.vmax_out, (unsigned long long)__double_as_longlong(double(m)));
+            atomicMax(a.vmax_out + (blockIdx.x & (kVmaxSlots - 1)),
+                      (unsigned long long)__double_as_longlong(double(m)));
         }
     }
 }
@@ -683,15 +694,15 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
 
 size_t mfma_args_bytes() { return sizeof(MfmaArgs); }
 
-// Batches use the default workgroup shape.
+// Batches use the default workgroup shape of their order.
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
                     void *out) {
-    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, kWaves);
+    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, default_waves(m.P));
     std::memcpy(out, &a, sizeof(a));
 }
 
 int mfma_tiles(const DevMesh &m) {
-    const int eb = mfma_elements_per_block(m.P, kWaves);
+    const int eb = mfma_elements_per_block(m.P, default_waves(m.P));
     return (m.K + eb - 1) / eb;
 }
 
@@ -702,11 +713,13 @@ hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
         if (bf3)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, kWaves>), dim3(8 * chunk), dim3(64 * kWaves), 0,
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, default_waves(PP)>), dim3(8 * chunk),
+                               dim3(64 * default_waves(PP)), 0,
                                st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
                                nitems, chunk);
         else
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, kWaves>), dim3(8 * chunk), dim3(64 * kWaves), 0,
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, default_waves(PP)>), dim3(8 * chunk),
+                               dim3(64 * default_waves(PP)), 0,
                                st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
                                nitems, chunk);
         return hipGetLastError();
@@ -715,7 +728,7 @@ hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void
 
 hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
                              int stage, const MfmaStep &step, hipStream_t st) {
-    const int waves = m.waves_per_block ? m.waves_per_block : kWaves;
+    const int waves = m.waves_per_block ? m.waves_per_block : default_waves(m.P);
     MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step, waves);
     return with_order_m(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
