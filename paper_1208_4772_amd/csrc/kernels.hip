@@ -796,9 +796,9 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) 
 
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                         const void *eps, const void *Q, hipStream_t st) {
-    if (m.fp32 && !m.av) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st);
-    return m.fp32 ? stage_t<float>(m, Uin, Uout, R, rhs, stage, eps, Q, st)
-                  : stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
+    // FP32 (with or without viscosity): the matrix-core kernel; FP64: VALU
+    if (m.fp32) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st, eps, Q);
+    return stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }
 
 template <typename T>

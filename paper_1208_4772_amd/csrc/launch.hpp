@@ -93,8 +93,9 @@ struct MfmaStep {
     unsigned long long *vmax_out = nullptr;
 };
 // FP32 matrix-core stage kernel (no artificial viscosity)
-hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
-                             int stage, const MfmaStep &step, hipStream_t st);
+hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                             const MfmaStep &step, hipStream_t st, const void *eps = nullptr,
+                             const void *Q = nullptr);
 int mfma_curved_bit();
 // batched meshes: per-(mesh, stage) argument records in device memory and a
 // work list of (record, tile) items, all meshes of order P

@@ -86,6 +86,8 @@ struct MfmaArgs {
     const float *__restrict__ geoC;    // [Kc][4 Np + 9 Nfp]
     const float *__restrict__ opsA;    // [MT][KS][64] A operand in lane order
     const float *__restrict__ ops;     // Dr | Ds (row-major) for curved elements
+    const float *__restrict__ eps;     // [K] artificial viscosity (viscous handles)
+    const float *__restrict__ Q;       // [K][2][4][Np] sqrt(eps) grad U (viscous handles)
     double *__restrict__ scal;
     const unsigned long long *__restrict__ vmax_in;
     unsigned long long *__restrict__ vmax_out;
@@ -103,7 +105,7 @@ __device__ __forceinline__ int face_node_sel(int f, int j) {
 // Lax-Friedrichs face term of one face-node task, scaled by Fscale, into the
 // B operand.  CURVED: the tile holds curved elements, whose normals and
 // Fscale are per face node.
-template <int P, bool BF3, int W, bool CURVED>
+template <int P, bool BF3, int W, bool CURVED, bool AV>
 __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, const int el, const int q,
                                           const float (&upn)[4], const float *sU, const float (*sG)[16],
                                           const int4 *sC, const int *sFN, float *sBflat) {
@@ -140,6 +142,25 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
     const float lam = lm > lp ? lm : lp;
 #pragma unroll
     for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
+    if constexpr (AV) {
+        // viscous face term with the central flux: (sigma Q)* . n - (sigma Q)- . n,
+        // (sigma Q)* the mean of both sides inside, the interior value on a
+        // boundary (so no contribution there)
+        if (code == BC_INTERIOR) {
+            const int j = q - f * Nfp;
+            const long km = k0 + el;
+            const long kn = f == 0 ? cv.x : (f == 1 ? cv.y : cv.z);
+            const int vp = sFN[face_nbr_face(cv.w, f) * Nfp + Nfp - 1 - j];
+            const float sm = fsqrt(a.eps[km]), sp = fsqrt(a.eps[kn]);
+            const float *Qm = a.Q + km * 8 * Np, *Qp = a.Q + kn * 8 * Np;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float vmv = sm * (nx * Qm[c * Np + vm] + ny * Qm[(4 + c) * Np + vm]);
+                const float vpv = sp * (nx * Qp[c * Np + vp] + ny * Qp[(4 + c) * Np + vp]);
+                d[c] += 0.5f * (vmv + vpv) - vmv;
+            }
+        }
+    }
     const f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
     *reinterpret_cast<f32x4 *>(&sBflat[((el >> 2) * KP + 2 * Np + q) * 16 + (el & 3) * 4]) = jv;
 }
@@ -147,7 +168,7 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
 // One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
 // arguments (single mesh) or in a device job table (batched meshes); its
 // fields are uniform across the block.
-template <int P, bool BF3, int W>
+template <int P, bool BF3, int W, bool AV>
 __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     using S = MShape<P, BF3, W>;
     constexpr int NTH = S::NTH;
@@ -256,8 +277,18 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         const float ir = rcp(u[0]);
         const float vx = u[1] * ir, vy = u[2] * ir;
         const float p = pressure_ir(a.g, u, ir);
-        const float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
-        const float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
+        float F[4] = {u[1], u[1] * vx + p, u[2] * vx, (u[3] + p) * vx};
+        float G[4] = {u[2], u[1] * vy, u[2] * vy + p, (u[3] + p) * vy};
+        if constexpr (AV) {
+            // viscous flux sigma Q (sigma = sqrt(eps) per element)
+            const float sig = fsqrt(a.eps[k0 + eln]);
+            const float *Qe = a.Q + (k0 + eln) * 8 * Np;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                F[c] -= sig * Qe[c * Np + in];
+                G[c] -= sig * Qe[(4 + c) * Np + in];
+            }
+        }
         const int t = eln >> 2, col = (eln & 3) * 4;
         f32x4 f, gg;
         curved_lane = sC[eln].w & kCurvedBit;
@@ -288,9 +319,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         if (task < ntask) {
             const int el = task / NF3, q = task - el * NF3;
             if (any_curved)
-                face_task<P, BF3, W, true>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
+                face_task<P, BF3, W, true, AV>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
             else
-                face_task<P, BF3, W, false>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
+                face_task<P, BF3, W, false, AV>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
         }
     }
     __syncthreads();
@@ -495,24 +526,25 @@ __device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * c
 // Occupancy request: as many resident waves per SIMD as the LDS allows (at
 // most 8), which caps the registers per lane at 512 / waves; the kernel
 // hides its memory latency with resident waves.
-template <int P, bool BF3, int W>
+template <int P, bool BF3, int W, bool AV = false>
 constexpr int waves_per_simd() {
     using S = MShape<P, BF3, W>;
     constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + S::EB * 16 + 256;
     constexpr int blocks = (160 * 1024) / lds;      // resident blocks per CU by LDS
     constexpr int waves = blocks * W / 4;           // per SIMD
-    // the BF16x3 product holds its hi/lo operand fragments in registers:
-    // at most 6 waves (85 registers) so that nothing spills
-    constexpr int cap = BF3 ? 6 : 8;
+    // the BF16x3 product holds its hi/lo operand fragments in registers, and
+    // the viscous terms need more too: at most 6 waves (85 registers) there,
+    // so that nothing spills
+    constexpr int cap = (BF3 || AV) ? 6 : 8;
     return waves >= cap ? cap : (waves < 1 ? 1 : waves);
 }
 
-template <int P, bool BF3, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W>())))
+template <int P, bool BF3, int W, bool AV>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W, AV>())))
 void k_stage_mfma(MfmaArgs a) {
     const int tile = xcd_item(a.chunk);
     if (tile >= a.nblocks) return;
-    stage_tile<P, BF3, W>(a, tile);
+    stage_tile<P, BF3, W, AV>(a, tile);
 }
 
 // Batched meshes of one order: work item = (job, tile); a job is one mesh's
@@ -524,7 +556,7 @@ void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restric
     const int w = xcd_item(chunk);
     if (w >= nitems) return;
     const int2 it = items[w];
-    stage_tile<P, BF3, W>(jobs[it.x], it.y);
+    stage_tile<P, BF3, W, false>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -658,7 +690,8 @@ int mfma_elements_per_block(int P, int waves) {
 int mfma_curved_bit() { return kCurvedBit; }
 
 static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                          const MfmaStep &step, int waves) {
+                          const MfmaStep &step, int waves, const void *eps = nullptr,
+                          const void *Q = nullptr) {
     MfmaArgs a;
     a.K = m.K;
     a.stage = stage;
@@ -682,6 +715,8 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
     a.geoC = m.geoC;
     a.opsA = m.bf3 ? reinterpret_cast<const float *>(m.opsB) : m.opsA;
     a.ops = m.ops32;
+    a.eps = static_cast<const float *>(eps);
+    a.Q = static_cast<const float *>(Q);
     a.scal = m.scal;
     a.vmax_in = step.vmax_in;
     a.vmax_out = step.vmax_out;
@@ -727,17 +762,26 @@ hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void
 }
 
 hipError_t launch_stage_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs,
-                             int stage, const MfmaStep &step, hipStream_t st) {
+                             int stage, const MfmaStep &step, hipStream_t st, const void *eps, const void *Q) {
     const int waves = m.waves_per_block ? m.waves_per_block : default_waves(m.P);
-    MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step, waves);
+    if (m.av && (!eps || !Q)) return hipErrorInvalidValue;
+    MfmaArgs a = make_args(m, Uin, Uout, R, rhs, stage, step, waves, eps, Q);
     return with_order_m(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         return with_waves(waves, [&](auto WC) {
             constexpr int W = decltype(WC)::value;
-            if (m.bf3)
-                hipLaunchKernelGGL((k_stage_mfma<P, true, W>), dim3(8 * a.chunk), dim3(64 * W), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_stage_mfma<P, false, W>), dim3(8 * a.chunk), dim3(64 * W), 0, st, a);
+            const dim3 grid(8 * a.chunk), block(64 * W);
+            if (m.av) {
+                if (m.bf3)
+                    hipLaunchKernelGGL((k_stage_mfma<P, true, W, true>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_stage_mfma<P, false, W, true>), grid, block, 0, st, a);
+            } else {
+                if (m.bf3)
+                    hipLaunchKernelGGL((k_stage_mfma<P, true, W, false>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_stage_mfma<P, false, W, false>), grid, block, 0, st, a);
+            }
             return hipGetLastError();
         });
     });
