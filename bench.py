@@ -212,7 +212,8 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=(f"k_stage<double,{case.P},false>" if args.precision == "fp64" else
-                            f"k_stage_mfma<{case.P},{'true' if args.precision == 'bf16x3' else 'false'}>"),
+                            f"k_stage_mfma<{case.P},{'true' if args.precision == 'bf16x3' else 'false'},"
+                            f"{tuned.get(args.precision, (0, 0.0))[0] or 4},false>"),
                     avg_launch_us=round(avg_s * 1e6, 3),
                     launches=5 * steps,
                     waves_per_block=tuned.get(args.precision, (0, 0.0))[0] or None,
