@@ -65,7 +65,9 @@ struct MShape {
     static constexpr int NT = (EB + 3) / 4;     // 16-column groups per block
     static constexpr int TF = EB * 4 * Np;      // state floats per block
     static constexpr int TPT = (EB * NF3 + NTH - 1) / NTH;  // face-node tasks per thread
+    static constexpr int GPT = (4 * EB + NTH - 1) / NTH;    // geometry float4 per thread
     static_assert(TF <= 4 * NTH, "one float4 per thread covers the tile");
+    static_assert(EB <= NTH, "one thread per element loads the connectivity");
     static_assert(16 * Np <= 16 * KP, "a column group's result fits in its B block");
 };
 
@@ -173,7 +175,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     using S = MShape<P, BF3, W>;
     constexpr int NTH = S::NTH;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KS32 = S::KS32, KP = S::KP, MT = S::MT;
-    constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF, TPT = S::TPT;
+    constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF, TPT = S::TPT, GPT = S::GPT;
 
     // ---- time step of this stage
     double dtd = 0.0;
@@ -232,7 +234,11 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     }
     const bool flat_ok = 4 * tid < nflt;
     const f32x4 u4 = *reinterpret_cast<const f32x4 *>(a.Uin + base + (flat_ok ? 4 * tid : 0));
-    const float4 g4 = a.geoA[k0 * 4 + min(tid, 4 * nel - 1)];
+    // geometry records, four float4 per element: where a tile holds more
+    // elements than a quarter of the threads (P = 1), a thread loads two
+    float4 g4[GPT];
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) g4[t] = a.geoA[k0 * 4 + min(tid + t * NTH, 4 * nel - 1)];
     const int4 c4 = a.conn[k0 + min(tid, nel - 1)];
     float upn[TPT][4];
 #pragma unroll
@@ -258,7 +264,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             sB[t][S::KV + rem / 16][rem % 16] = 0.f;
         }
     }
-    if (tid < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid] = g4;
+#pragma unroll
+    for (int t = 0; t < GPT; ++t)
+        if (tid + t * NTH < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid + t * NTH] = g4[t];
     if (tid < nel) sC[tid] = c4;
     if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
     // one barrier for the tile in LDS, which also tells whether it holds a

@@ -33,7 +33,8 @@ def test_batch_results_equal_alone_bitwise():
     import torch
     reqs = [("cylinder", 4, 0.02, 7, "fp32", 0.38), ("vortex", 2, 1.0, 12, "fp32", None),
             ("cylinder", 3, 0.03, 20, "fp32", 0.6), ("airfoil", 3, 0.01, 9, "fp32", 0.5),
-            ("cylinder", 5, 0.01, 11, "fp64", 0.3), ("cylinder", 3, 0.02, 6, "bf16x3", 0.45)]
+            ("cylinder", 5, 0.01, 11, "fp64", 0.3), ("cylinder", 3, 0.02, 6, "bf16x3", 0.45),
+            ("cylinder", 1, 0.05, 10, "fp32", 0.4)]
     late = ("vortex", 5, 0.3, 8, "fp32", None)
     b = dg().Batch(1 << 34, 8)
     live = {}

@@ -72,6 +72,10 @@ def meshes_for_rhs():
     out.append(("farfield_annulus_P3", lambda: meshgen.cylinder_annulus(20, 5, inner_bc=meshgen.BC_FARFIELD), 3,
                 meshgen.freestream_state(0.5, 5.0)))
     out.append(("airfoil_small_P3", lambda: meshgen.naca4_ogrid(40, 8), 3, meshgen.freestream_state(0.8, 1.25)))
+    # P = 1 tiles hold more elements than a quarter of the workgroup's
+    # threads: several tiles, walls and far field
+    out.append(("airfoil_small_P1", lambda: meshgen.naca4_ogrid(40, 8), 1, meshgen.freestream_state(0.66, 1.25)))
+    out.append(("cylinder_small_P1", lambda: meshgen.cylinder_annulus(24, 6), 1, meshgen.freestream_state(0.38)))
     return out
 
 
@@ -188,12 +192,16 @@ def test_bench_config_full_size(precision):
     assert abs(st.t - info["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * info["t"]
 
 
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_viscosity_and_av_rhs_match_oracle(precision):
+def test_viscosity_and_av_rhs_match_oracle(precision, P):
     mesh = meshgen.naca4_ogrid(40, 8)
     q = meshgen.freestream_state(0.8, 1.25)
-    P = 3
-    o, s, x, y = case_pair(mesh, P, q, precision, av=True, av_kappa=1.0, av_eps0=0.3)
+    # at P = 1 the default s0 = -4 log10 P = 0 sets the threshold at a
+    # top-mode energy fraction of 0.1, above what the density step reaches
+    # on these elements; s0 = -1 brings the sensor in
+    extra = {"av_s0": -1.0} if P == 1 else {}
+    o, s, x, y = case_pair(mesh, P, q, precision, av=True, av_kappa=1.0, av_eps0=0.3, **extra)
     U = perturbed_state(x, y, q, amp=0.02)
     # a density step across x = 0.4 triggers the sensor near the airfoil
     U[:, 0] *= np.where(x < 0.4, 1.0, 2.5)
@@ -207,7 +215,7 @@ def test_viscosity_and_av_rhs_match_oracle(precision):
                                atol=(1e-12 if precision == "fp64" else 1e-4) * eps_ref.max())
     got = s.rhs(s.state(U)).double().cpu().numpy()
     err = rel_l2(got, o.rhs(U))
-    print(f"[airfoil AV rhs {precision}] rel L2 {err:.3e}, {int((eps_ref > 0).sum())} viscous elements")
+    print(f"[airfoil AV rhs {precision} P={P}] rel L2 {err:.3e}, {int((eps_ref > 0).sum())} viscous elements")
     assert err <= TOL[precision]
 
 
@@ -288,3 +296,28 @@ def test_autotune_keeps_results_bitwise():
     assert torch.equal(r0, r1) and torch.equal(U0, U1)
     f = dg().Solver.from_case(case, "fp64")
     assert f.autotune(f.state(case.U0)) == (0, 0.0)
+
+
+@pytest.mark.parametrize("av", [True, False], ids=["av", "inviscid"])
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_airfoil_run_matches_oracle(precision, P, av):
+    """12 CFL steps from the impulsive start on a small airfoil O-grid (the
+    shape of the serving requests), with and without the viscous terms:
+    state update and simulated time against the oracle."""
+    import torch
+    mesh = meshgen.naca4_ogrid(40, 8)
+    q = meshgen.freestream_state(0.66, 1.25)
+    kw = dict(av_kappa=1.0, av_eps0=0.3) if av else {}
+    o, s, x, y = case_pair(mesh, P, q, precision, av=av, **kw)
+    U0 = meshgen.uniform((mesh.K, x.shape[1]), q)
+    Ur, info = o.run(U0, 12)
+    Ud = s.state(U0)
+    st = s.run(Ud, 12, check=False)
+    torch.cuda.synchronize()
+    got = Ud.double().cpu().numpy()
+    assert np.all(np.isfinite(Ur)) and st.status == 0, st.status
+    err = rel_l2(got - U0, Ur - U0)
+    print(f"[airfoil {'AV' if av else 'inviscid'} run {precision} P={P}] rel L2 of the update {err:.3e}")
+    assert err <= (FP64_TOL * 10 if precision == "fp64" else 1e-3)
+    assert abs(st.t - info["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * info["t"]
