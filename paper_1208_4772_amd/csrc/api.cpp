@@ -308,10 +308,11 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         dm.ops32 = ops32;
         // matrix-core kernel tables: packed connectivity, affine records for
         // every element, per-node records for curved ones, A operand
-        int *conn4_d, *cidx_d, *flags_d;
+        int *conn4_d, *cidx_d, *cpre_d, *flags_d;
         float *geoA_d, *opsA_d;
         const size_t nA = mfma_opsA_floats(P);
         if ((rc = m->alloc(&conn4_d, size_t(K) * 4)) || (rc = m->alloc(&cidx_d, size_t(K))) ||
+            (rc = m->alloc(&cpre_d, size_t(K) + 1)) ||
             (rc = m->alloc(&flags_d, size_t(K))) || (rc = m->alloc(&geoA_d, size_t(K) * 16)) ||
             (rc = m->alloc(&opsA_d, nA)))
             return cleanup(rc);
@@ -329,11 +330,15 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
             dm.opsB = opsB_d;
         }
         SETUP_TRY(launch_affine_flags(dm, flags_d, st));
-        std::vector<int> flags(K), cidx(K);
+        std::vector<int> flags(K), cidx(K), cpre(size_t(K) + 1);
         SETUP_TRY(hipMemcpyAsync(flags.data(), flags_d, sizeof(int) * K, hipMemcpyDeviceToHost, st));
         SETUP_TRY(hipStreamSynchronize(st));
         int Kc = 0;
-        for (long k = 0; k < K; ++k) cidx[k] = flags[k] ? -1 : Kc++;
+        for (long k = 0; k < K; ++k) {
+            cpre[k] = Kc;
+            cidx[k] = flags[k] ? -1 : Kc++;
+        }
+        cpre[K] = Kc;
         std::vector<int> conn4(size_t(K) * 4);
         for (long k = 0; k < K; ++k) {
             conn4[k * 4 + 0] = nbr[k * 3 + 0];
@@ -345,9 +350,11 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         float *geoC_d;
         if ((rc = m->alloc(&geoC_d, size_t(Kc) * (4 * Np + 9 * Nfp)))) return cleanup(rc);
         SETUP_TRY(hipMemcpyAsync(cidx_d, cidx.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        SETUP_TRY(hipMemcpyAsync(cpre_d, cpre.data(), sizeof(int) * (size_t(K) + 1), hipMemcpyHostToDevice, st));
         SETUP_TRY(launch_pack_geometry(dm, cidx_d, geoA_d, geoC_d, st));
         dm.conn4 = conn4_d;
         dm.cidx = cidx_d;
+        dm.cpre = cpre_d;
         dm.geoA = geoA_d;
         dm.geoC = geoC_d;
         dm.opsA = opsA_d;
@@ -758,7 +765,7 @@ int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *by
     b += k * Np * 2 * 8;                                          // node coordinates
     b += k * (4 * Np + 9 * Nfp + Np + 1) * 8;                     // FP64 geometry, mass weights, eps_max
     if (f32)
-        b += k * (4 * Np + 9 * Nfp + 1) * 4 + k * (4 + 1 + 1) * 4 + k * 16 * 4  // FP32 copies, conn, flags
+        b += k * (4 * Np + 9 * Nfp + 1) * 4 + k * (4 + 1 + 1 + 1) * 4 + k * 16 * 4  // FP32 copies, conn, flags
              + k * (4 * Np + 9 * Nfp) * 4;                        // curved records (upper bound)
     const size_t state = k * 4 * Np * s;
     size_t work = 3 * align256(state);

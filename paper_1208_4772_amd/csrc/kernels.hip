@@ -453,8 +453,10 @@ __global__ void k_pack_geometry(int K, const double *__restrict__ geo, const dou
     for (int m = 0; m < 4; ++m) ga[m] = float(geo[(k * 4 + m) * Np]);
     for (int f = 0; f < 3; ++f)
         for (int m = 0; m < 3; ++m) ga[4 + 3 * f + m] = float(fgeo[(k * 3 + m) * NF3 + f * Nfp]);
-    ga[13] = ga[14] = ga[15] = 0.f;
     const int c = cidx[k];
+    // slot 13: 1 for a curved element (its per-node record is in geoC)
+    ga[13] = c >= 0 ? 1.f : 0.f;
+    ga[14] = ga[15] = 0.f;
     if (c >= 0) {
         float *gc = geoC + (long)c * (4 * Np + 9 * Nfp);
         for (int m = 0; m < 4; ++m)

@@ -45,6 +45,7 @@ struct DevMesh {
     const int *conn4 = nullptr;     // [K][4] nbr0, nbr1, nbr2, packed face info
     const float *geoA = nullptr;    // [K][16] affine geometry record
     const int *cidx = nullptr;      // [K] curved slot or -1
+    const int *cpre = nullptr;      // [K + 1] number of curved elements before element k
     const float *geoC = nullptr;    // [Kc][4 Np + 9 Nfp] curved geometry
     const float *opsA = nullptr;    // MFMA A operand table
     const unsigned *opsB = nullptr; // BF16x3 A operand table (hi and lo splits)

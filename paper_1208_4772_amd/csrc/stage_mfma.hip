@@ -85,6 +85,7 @@ struct MfmaArgs {
     const int4 *__restrict__ conn;     // [K] {nbr0, nbr1, nbr2, packed face info}
     const float4 *__restrict__ geoA;   // [K][4]: rx sx ry sy | (nx ny Fscale) x 3 | pad
     const int *__restrict__ cidx;      // [K] curved slot or -1
+    const int *__restrict__ cpre;      // [K + 1] curved elements before element k
     const float *__restrict__ geoC;    // [Kc][4 Np + 9 Nfp]
     const float *__restrict__ opsA;    // [MT][KS][64] A operand in lane order
     const float *__restrict__ ops;     // Dr | Ds (row-major) for curved elements
@@ -110,7 +111,7 @@ __device__ __forceinline__ int face_node_sel(int f, int j) {
 template <int P, bool BF3, int W, bool CURVED, bool AV>
 __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, const int el, const int q,
                                           const float (&upn)[4], const float *sU, const float (*sG)[16],
-                                          const int4 *sC, const int *sFN, float *sBflat) {
+                                          const int4 cv, const int *sFN, float *sBflat) {
     using S = MShape<P, BF3, W>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KP = S::KP;
     const int f = q / Nfp;
@@ -118,7 +119,6 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
     float um[4], up[4], d[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) um[c] = sU[(el * 4 + c) * Np + vm];
-    const int4 cv = sC[el];
     float nx, ny, fs;
     if (CURVED && (cv.w & kCurvedBit)) {
         const float *gc = a.geoC + (long)a.cidx[k0 + el] * (4 * Np + 9 * Nfp) + 4 * Np;
@@ -177,39 +177,24 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KS = S::KS, KS32 = S::KS32, KP = S::KP, MT = S::MT;
     constexpr int EW = S::EW, EB = S::EB, NT = S::NT, TF = S::TF, TPT = S::TPT, GPT = S::GPT;
 
-    // ---- time step of this stage
+    // ---- time step of this stage, requested now: the first stage of a step
+    // reduces the CFL-bound slots (after the first barrier, when they have
+    // arrived), the others read the step the first one booked
+    unsigned long long vb = 0;
     double dtd = 0.0;
-    if (a.cfl_mode) {
-        // the bound is the maximum over the slots (non-negative doubles order
-        // like their bit patterns); every wavefront reduces them itself
-        unsigned long long vb = a.vmax_in[threadIdx.x & (kVmaxSlots - 1)];
-        for (int off = kVmaxSlots / 2; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(vb, off);
-            vb = o > vb ? o : vb;
-        }
-        const double vmax = __longlong_as_double((long long)vb);
-        dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * (1.0 / vmax);
-        if (tile == 0 && threadIdx.x < kVmaxSlots) {
-            if (threadIdx.x == 0) {
-                a.scal[S_DT] = dtd;
-                a.scal[S_T] += dtd;
-                a.scal[S_DTMIN] = dtd < a.scal[S_DTMIN] ? dtd : a.scal[S_DTMIN];
-                a.scal[S_DTMAX] = dtd > a.scal[S_DTMAX] ? dtd : a.scal[S_DTMAX];
-                a.scal[S_STEPS] += 1.0;
-            }
-            a.vmax_out[threadIdx.x] = 0ull;
-        }
-    } else if (a.mode) {
+    if (a.cfl_mode)
+        vb = a.vmax_in[threadIdx.x & (kVmaxSlots - 1)];
+    else if (a.mode)
         dtd = a.scal[S_DT];
-    }
 
     const long k0 = (long)tile * EB;
     const int nel = (int)min((long)EB, (long)a.K - k0);
+    // whether the tile holds a curved element (uniform: two scalar loads)
+    const bool any_curved = a.cpre[k0 + nel] != a.cpre[k0];
 
     __shared__ float sU[TF];
     __shared__ float sB[NT][KP][16];    // B operand; afterwards the result of that column group
     __shared__ float sG[EB][16];
-    __shared__ int4 sC[EB];
     __shared__ float sRed[W];
     __shared__ int sFN[NF3];              // face node ids, face-major, counter-clockwise
 
@@ -222,10 +207,13 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     auto res = [&](int el, int off) -> float & { return (&sB[el >> 2][0][0])[(el & 3) * 4 * Np + off]; };
 
     // ---- loads.  Every address is clamped into the tile so that the loads
-    // need no branches; the neighbour face traces for the face-node tasks
-    // this thread will handle (task = element * 3 Nfp + face node; tasks tid,
-    // tid + 256, ...) are requested as soon as the connectivity arrives, so
-    // their latency overlaps the tile load and the pointwise phase.
+    // need no branches.  Order matters: a wavefront's memory counter retires
+    // loads in issue order, so what the first barrier needs (the tile and
+    // its geometry) goes first, then the neighbour face traces for the
+    // face-node tasks this thread will handle (task = element * 3 Nfp + face
+    // node; tasks tid, tid + 64 W, ...; needed in the face phase), then the
+    // Runge-Kutta register (needed in the epilogue): the last two stay in
+    // flight across the barrier and the pointwise phase.
     int4 tconn[TPT];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -239,7 +227,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     float4 g4[GPT];
 #pragma unroll
     for (int t = 0; t < GPT; ++t) g4[t] = a.geoA[k0 * 4 + min(tid + t * NTH, 4 * nel - 1)];
-    const int4 c4 = a.conn[k0 + min(tid, nel - 1)];
     float upn[TPT][4];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -267,11 +254,34 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
 #pragma unroll
     for (int t = 0; t < GPT; ++t)
         if (tid + t * NTH < 4 * nel) reinterpret_cast<float4 *>(&sG[0][0])[tid + t * NTH] = g4[t];
-    if (tid < nel) sC[tid] = c4;
     if (flat_ok) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = u4;
-    // one barrier for the tile in LDS, which also tells whether it holds a
-    // curved element
-    const bool any_curved = __syncthreads_or(tid < nel && (c4.w & kCurvedBit));
+    __syncthreads();
+
+    if (a.cfl_mode) {
+        // the bound is the maximum over the slots (non-negative doubles order
+        // like their bit patterns); every wavefront reduces them itself
+        for (int off = kVmaxSlots / 2; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(vb, off);
+            vb = o > vb ? o : vb;
+        }
+        const double vmax = __longlong_as_double((long long)vb);
+        dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl * (1.0 / vmax);
+        if (tile == 0 && threadIdx.x < kVmaxSlots) {
+            if (threadIdx.x == 0) {
+                a.scal[S_DT] = dtd;
+                a.scal[S_T] += dtd;
+                a.scal[S_DTMIN] = dtd < a.scal[S_DTMIN] ? dtd : a.scal[S_DTMIN];
+                a.scal[S_DTMAX] = dtd > a.scal[S_DTMAX] ? dtd : a.scal[S_DTMAX];
+                a.scal[S_STEPS] += 1.0;
+            }
+            a.vmax_out[threadIdx.x] = 0ull;
+        }
+        // the same in every lane: keep it in scalar registers
+        const unsigned long long db = (unsigned long long)__double_as_longlong(dtd);
+        const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(db));
+        const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(db >> 32));
+        dtd = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
 
     // ---- pointwise fluxes (lane = element * Np + node within the wavefront)
     const int le = lane / Np, in = lane - le * Np;
@@ -299,7 +309,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         }
         const int t = eln >> 2, col = (eln & 3) * 4;
         f32x4 f, gg;
-        curved_lane = sC[eln].w & kCurvedBit;
+        curved_lane = any_curved && sG[eln][13] != 0.f;
         if (!curved_lane) {
             const float rx = sG[eln][0], sx = sG[eln][1], ry = sG[eln][2], sy = sG[eln][3];
 #pragma unroll
@@ -327,11 +337,40 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         if (task < ntask) {
             const int el = task / NF3, q = task - el * NF3;
             if (any_curved)
-                face_task<P, BF3, W, true, AV>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
+                face_task<P, BF3, W, true, AV>(a, k0, el, q, upn[t], sU, sG, tconn[t], sFN, &sB[0][0][0]);
             else
-                face_task<P, BF3, W, false, AV>(a, k0, el, q, upn[t], sU, sG, sC, sFN, &sB[0][0][0]);
+                face_task<P, BF3, W, false, AV>(a, k0, el, q, upn[t], sU, sG, tconn[t], sFN, &sB[0][0][0]);
         }
     }
+    // the A operand of the product (the same few KB for every block, so it
+    // comes from the caches; FP32: four fragments per lane per 16-byte load;
+    // BF16x3: hi and lo splits).  A tile without curved elements requests it
+    // before the barrier, so that its latency overlaps the other
+    // wavefronts' face tasks; a curved tile after its volume phase, which
+    // needs the registers.  At P = 5 the operand (30 fragments per lane)
+    // does not fit the register budget that early, and is requested just
+    // before the product.
+    constexpr bool early_A = P <= 4;
+    constexpr int NZ = MT * KS, NG4 = (NZ + 3) / 4;
+    f32x4 ga4[BF3 ? 1 : NG4];
+    u32x4 ah[BF3 ? MT * KS32 : 1], al[BF3 ? MT * KS32 : 1];
+    auto load_A = [&]() {
+        if (wave < NT) {
+            if constexpr (!BF3) {
+                const f32x4 *ga = reinterpret_cast<const f32x4 *>(a.opsA);
+#pragma unroll
+                for (int g = 0; g < NG4; ++g) ga4[g] = ga[g * 64 + lane];
+            } else {
+                const u32x4 *opsB = reinterpret_cast<const u32x4 *>(a.opsA);
+#pragma unroll
+                for (int z = 0; z < MT * KS32; ++z) {
+                    ah[z] = opsB[(2 * z) * 64 + lane];
+                    al[z] = opsB[(2 * z + 1) * 64 + lane];
+                }
+            }
+        }
+    };
+    if (early_A && !any_curved) load_A();
     __syncthreads();
 
     // ---- curved elements: volume term with per-node metrics (VALU), kept
@@ -367,8 +406,10 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             *reinterpret_cast<f32x4 *>(&sB[t][in][col]) = z;
             *reinterpret_cast<f32x4 *>(&sB[t][Np + in][col]) = z;
         }
+        if (early_A) load_A();
         __syncthreads();
     }
+    if (!early_A) load_A();
 
     // ---- the contraction on the matrix cores: wave w takes column groups
     // w, w+4, ...; result row = node, column = 4 * element + field.  The
@@ -381,18 +422,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             acc2[mt] = f32x4{0, 0, 0, 0};
         }
         if constexpr (!BF3) {
-            // A operand fragments straight from global memory (the same few
-            // KB for every block, so they stay in the caches), four per lane
-            // per 16-byte load
-            constexpr int NZ = MT * KS, NG4 = (NZ + 3) / 4;
-            float av[4 * NG4];
-            const f32x4 *ga = reinterpret_cast<const f32x4 *>(a.opsA);
-#pragma unroll
-            for (int g = 0; g < NG4; ++g) {
-                const f32x4 v = ga[g * 64 + lane];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) av[4 * g + j] = v[j];
-            }
             // two independent accumulation chains per output tile (even and
             // odd k-steps) halve the dependent-MFMA latency
 #pragma unroll
@@ -401,9 +430,11 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     if (ks & 1)
-                        acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt * KS + ks], b, acc2[mt], 0, 0, 0);
+                        acc2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga4[(mt * KS + ks) / 4][(mt * KS + ks) % 4], b,
+                                                                        acc2[mt], 0, 0, 0);
                     else
-                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt * KS + ks], b, acc[mt], 0, 0, 0);
+                        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga4[(mt * KS + ks) / 4][(mt * KS + ks) % 4], b,
+                                                                       acc[mt], 0, 0, 0);
                 }
             }
         } else {
@@ -413,13 +444,6 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
             // Lane l holds k-slots 8 (l / 16) + i, i < 8, of row/column l % 16
             // in both operands, so the slot-to-k assignment is the same on
             // both sides of the product.
-            const u32x4 *opsB = reinterpret_cast<const u32x4 *>(a.opsA);
-            u32x4 ah[MT * KS32], al[MT * KS32];
-#pragma unroll
-            for (int z = 0; z < MT * KS32; ++z) {
-                ah[z] = opsB[(2 * z) * 64 + lane];
-                al[z] = opsB[(2 * z + 1) * 64 + lane];
-            }
 #pragma unroll
             for (int ks = 0; ks < KS32; ++ks) {
                 bf16x8 bh, bl;
@@ -472,7 +496,9 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         } else {
             const float dt = float(dtd);
             const f32x4 rn = a.stage == 0 ? dt * rh : a.ra * r4 + dt * rh;
-            const f32x4 un = u4 + a.rb * rn;
+            // the stage's input state, still in LDS (kept there rather than in
+            // registers through the product)
+            const f32x4 un = *reinterpret_cast<const f32x4 *>(&sU[4 * tid]) + a.rb * rn;
             *reinterpret_cast<f32x4 *>(a.R + base + 4 * tid) = rn;
             *reinterpret_cast<f32x4 *>(a.Uout + base + 4 * tid) = un;
             if (a.cfl_accum) *reinterpret_cast<f32x4 *>(&sU[4 * tid]) = un;
@@ -537,7 +563,7 @@ __device__ __forceinline__ int xcd_item(int chunk) { return (blockIdx.x % 8) * c
 template <int P, bool BF3, int W, bool AV = false>
 constexpr int waves_per_simd() {
     using S = MShape<P, BF3, W>;
-    constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + S::EB * 16 + 256;
+    constexpr int lds = S::TF * 4 + S::NT * S::KP * 64 + S::EB * 64 + 256;
     constexpr int blocks = (160 * 1024) / lds;      // resident blocks per CU by LDS
     constexpr int waves = blocks * W / 4;           // per SIMD
     // the BF16x3 product holds its hi/lo operand fragments in registers, and
@@ -720,6 +746,7 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
     a.conn = reinterpret_cast<const int4 *>(m.conn4);
     a.geoA = reinterpret_cast<const float4 *>(m.geoA);
     a.cidx = m.cidx;
+    a.cpre = m.cpre;
     a.geoC = m.geoC;
     a.opsA = m.bf3 ? reinterpret_cast<const float *>(m.opsB) : m.opsA;
     a.ops = m.ops32;
