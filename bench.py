@@ -172,6 +172,7 @@ def main():
         f"steps={steps} warmup={args.warmup}")
 
     tuned = {}
+    final = {}
 
     def timed_run(precision, nsteps, warmup):
         sol = dg.Solver.from_case(case, precision, device="cuda:0")
@@ -188,6 +189,7 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ok = bool(torch.isfinite(U).all().item())
+        final[precision] = U.double().cpu().numpy()
         sol.close()
         return wall, st, ok
 
@@ -243,6 +245,20 @@ def main():
                                  finite=ok64)
         out["fp32_over_fp64_plain"] = round(value / out["fp64_plain"]["value"], 3)
         log(f"fp64 plain: {w64 * 1e3:.2f} ms -> {out['fp64_plain']['value']:.4e} DOF-updates/s")
+        # the timed run's final state against the FP64 run's (which matches
+        # the FP64 oracle to 1e-12): the reduced-precision error at that time
+        from paper_1208_4772_amd import accuracy
+        geo = accuracy.Geometry(case)
+        acc = dict(vs="fp64_plain", step=steps, t=st.t,
+                   **accuracy.state_errors(final[args.precision], final["fp64"]),
+                   entropy_error=geo.entropy_error(final[args.precision], case.freestream),
+                   entropy_error_fp64=geo.entropy_error(final["fp64"], case.freestream))
+        loads = geo.wall_loads(final[args.precision], case.freestream)
+        if loads is not None:
+            acc["wall"] = loads
+            acc["wall_fp64"] = geo.wall_loads(final["fp64"], case.freestream)
+        out["accuracy"] = acc
+        log(f"accuracy vs fp64 plain: {acc}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
         log(f"cpu baseline: {out['cpu_baseline']}")

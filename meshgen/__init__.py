@@ -8,5 +8,6 @@ from .meshes import (BC_FARFIELD, BC_INTERIOR, BC_WALL, FACE_VERTS, Mesh,  # noq
                      naca_point, node_coordinates, periodic_square,
                      permute_elements)
 from .flows import (GAMMA, cylinder_potential, freestream_state,  # noqa: F401
-                    isentropic_vortex, primitive_to_conserved, uniform)
+                    isentropic_vortex, primitive_to_conserved, uniform,
+                    wall_damped)
 from .cases import CASES, make_case  # noqa: F401

@@ -47,6 +47,13 @@ class Case:
 CASES = ("vortex", "cylinder", "airfoil", "roofline", "roofline_curved")
 
 
+def _wall_points(mesh):
+    """Vertices of the wall faces (x, y)."""
+    k, f = np.nonzero(mesh.bc == meshes.BC_WALL)
+    v = mesh.EToV[k[:, None], np.asarray(meshes.FACE_VERTS)[f]]
+    return mesh.VX[v].ravel(), mesh.VY[v].ravel()
+
+
 def _np_of(P):
     return (P + 1) * (P + 2) // 2
 
@@ -55,8 +62,9 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
               mach: float | None = None, steps: int | None = None,
               start: str = "freestream") -> Case:
     """Build one of ``CASES``.  ``scale`` < 1 shrinks the element count.
-    ``start="potential"`` starts the cylinder from the wall-compatible
-    potential flow instead of the impulsive freestream."""
+    ``start`` for the cylinder and the airfoil: "freestream" (impulsive),
+    "potential" (cylinder only: the wall-compatible potential flow) or
+    "damped" (the freestream with its velocity damped to rest at the wall)."""
     r = np.asarray(r, dtype=np.float64)
     s = np.asarray(s, dtype=np.float64)
     if name == "vortex":
@@ -79,6 +87,8 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
         q = flows.freestream_state(M, 0.0)
         if start == "potential":
             U0 = np.ascontiguousarray(flows.cylinder_potential(x, y, M))
+        elif start == "damped":
+            U0 = flows.wall_damped(x, y, *_wall_points(mesh), q)
         else:
             U0 = flows.uniform((mesh.K, x.shape[1]), q)
         return Case(name, P, mesh, x, y, U0, q, steps=2000 if steps is None else steps,
@@ -92,7 +102,12 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
         x, y = meshes.node_coordinates(mesh, r, s)
         M = 0.8 if mach is None else mach
         q = flows.freestream_state(M, 1.25)
-        U0 = flows.uniform((mesh.K, x.shape[1]), q)
+        if start == "damped":
+            U0 = flows.wall_damped(x, y, *_wall_points(mesh), q)
+        elif start == "freestream":
+            U0 = flows.uniform((mesh.K, x.shape[1]), q)
+        else:
+            raise ValueError(f"start {start!r} is not available for the airfoil")
         return Case(name, P, mesh, x, y, U0, q, steps=2000 if steps is None else steps,
                     av=True, av_eps0=0.3, av_kappa=1.0,
                     info=dict(mach=M, alpha=1.25))

@@ -47,6 +47,24 @@ def cylinder_potential(x, y, mach: float, radius: float = 1.0, gamma=GAMMA):
     return primitive_to_conserved(rho, u, v, rho ** gamma / gamma, gamma)
 
 
+def wall_damped(x, y, wall_x, wall_y, q, delta: float = 0.2, gamma=GAMMA):
+    """Smooth start for flow past a body: the freestream q with its velocity
+    scaled by 1 - exp(-(d / delta)^2), d the distance to the nearest of the
+    given wall points, at the freestream density and pressure.  The fluid at
+    the wall starts at rest (compatible with the slip wall) and the flow
+    reaches the freestream a few delta away, so the start launches no
+    impulsive wave from the wall."""
+    from scipy.spatial import cKDTree
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    d, _ = cKDTree(np.c_[np.ravel(wall_x), np.ravel(wall_y)]).query(np.c_[x.ravel(), y.ravel()])
+    f = 1.0 - np.exp(-(d.reshape(x.shape) / delta) ** 2)
+    q = np.asarray(q, dtype=np.float64)
+    rho, u, v = q[0], q[1] / q[0], q[2] / q[0]
+    p = (gamma - 1.0) * (q[3] - 0.5 * rho * (u * u + v * v))
+    return np.ascontiguousarray(primitive_to_conserved(rho + 0 * x, u * f, v * f, p + 0 * x, gamma))
+
+
 def uniform(shape_KNp, q):
     """Fill (K,4,Np) with the constant state q (4,)."""
     K, Np = shape_KNp

@@ -84,9 +84,10 @@ def build_case(req: Request):
     """Mesh, node positions and freestream start of a request (host)."""
     rr, ss = dg.reference_nodes(req.P)
     scale = req.K_target / _DEFAULT_K[req.kind]
-    # cylinders start from the wall-compatible potential flow: the impulsive
-    # start drives the coarse high-order meshes of the mix to rho, p <= 0
-    start = "potential" if req.kind == "cylinder" else "freestream"
+    # a start compatible with the slip wall (cylinders: the potential flow;
+    # airfoils: the freestream damped to rest at the wall): the impulsive
+    # start drives many meshes of the mix to rho, p <= 0
+    start = "potential" if req.kind == "cylinder" else "damped"
     case = meshgen.make_case(req.kind, rr, ss, scale=scale, P=req.P, mach=req.mach, steps=req.steps,
                              start=start)
     case.av = True if req.av is None else bool(req.av)
@@ -224,7 +225,7 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--max-slots", type=int, default=16)
     ap.add_argument("--chunk-steps", type=int, default=50)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     a = ap.parse_args(argv)
     t = time.perf_counter()
     reqs = make_requests(a.requests, a.mean_gap, a.seed)

@@ -122,3 +122,26 @@ def test_cylinder_potential_start():
            + (meshgen.cylinder_potential(x, y + h, 0.6)[2] / meshgen.cylinder_potential(x, y + h, 0.6)[0]
               - meshgen.cylinder_potential(x, y - h, 0.6)[2] / meshgen.cylinder_potential(x, y - h, 0.6)[0])) / (2 * h)
     np.testing.assert_allclose(div, 0, atol=1e-8)
+
+
+def test_wall_damped_start():
+    """At rest on the wall points, the freestream far from them, the
+    freestream density and pressure everywhere."""
+    r, s = np.array([-1.0, 1.0, -1.0]), np.array([-1.0, -1.0, 1.0])
+    case = meshgen.make_case("airfoil", r, s, scale=0.01, start="damped")
+    q = case.freestream
+    U = case.U0
+    rho, u, v = U[:, 0], U[:, 1] / U[:, 0], U[:, 2] / U[:, 0]
+    p = 0.4 * (U[:, 3] - 0.5 * rho * (u * u + v * v))
+    np.testing.assert_allclose(rho, 1.0, rtol=1e-15)
+    np.testing.assert_allclose(p, 1 / 1.4, rtol=1e-13)
+    # P = 1 nodes are the vertices: the wall vertices start at rest
+    k, f = np.nonzero(case.mesh.bc == meshgen.BC_WALL)
+    wall_nodes = np.array([meshgen.FACE_VERTS[ff][0] for ff in f])
+    np.testing.assert_allclose(u[k, wall_nodes], 0.0, atol=1e-14)
+    np.testing.assert_allclose(v[k, wall_nodes], 0.0, atol=1e-14)
+    far = np.hypot(case.x, case.y) > 10
+    np.testing.assert_allclose(u[far], q[1], rtol=1e-12)
+    np.testing.assert_allclose(v[far], q[2], rtol=1e-12)
+    with pytest.raises(ValueError):
+        meshgen.make_case("airfoil", r, s, scale=0.01, start="potential")
