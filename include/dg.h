@@ -212,10 +212,11 @@ int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *by
  * A batch holds up to max_slots independent solves (each a dg_mesh with its
  * own state U and work buffer, all on one device) whose summed footprints
  * stay within hbm_budget_bytes.  dg_batch_advance moves every active slot
- * forward in lockstep: for each order P one launch per RK stage covers the
- * tiles of all FP32 (non-viscous) slots of that order, each with its own
- * CFL time step computed on the device; other slots are stepped one by one
- * in the same stream.  Two steps are captured in a hipGraph and replayed
+ * forward in lockstep: for each order P, precision mode and viscosity
+ * setting one launch per RK stage covers the tiles of all FP32 slots of
+ * that kind (viscous slots add one sensor and one gradient launch per
+ * stage over all of them), each with its own CFL time step computed on the
+ * device; FP64 slots are stepped one by one in the same stream.  Two steps are captured in a hipGraph and replayed
  * while the membership does not change.  The result of every slot is
  * bit-identical to running it alone with dg_run.  Slots join (admit) and
  * leave (release) between calls, so solves that arrive while others are

@@ -447,22 +447,34 @@ static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st,
     void *in[5] = {U, A, B, A, B};
     void *out[5] = {A, B, A, B, U};
     if (fused_parity >= 0) {
-        // matrix-core path: dt comes from the CFL bound the previous step's
-        // last stage left in vmax[parity]; this step's last stage fills the other slot
+        // matrix-core path: the first stage turns the CFL bound in
+        // vmax[parity] into dt and clears vmax[1 - parity]; without
+        // viscosity the previous step's last stage left the bound (of this
+        // step's state), with viscosity this step's first sensor does (it
+        // needs the viscosity of this state)
+        unsigned long long *vin = m->dm.vmax + fused_parity * kVmaxSlots;
+        unsigned long long *vout = m->dm.vmax + (1 - fused_parity) * kVmaxSlots;
         for (int s = 0; s < 5; ++s) {
             MfmaStep ms;
             ms.dt_fixed = dt;
             if (s == 0) {
                 ms.cfl_mode = 1;
-                ms.vmax_in = m->dm.vmax + fused_parity * kVmaxSlots;
-                ms.vmax_out = m->dm.vmax + (1 - fused_parity) * kVmaxSlots;
+                ms.vmax_in = vin;
+                ms.vmax_out = vout;
             }
-            if (s == 4) {
+            if (s == 4 && !m->dm.av) {
                 ms.cfl_accum = 1;
-                ms.vmax_out = m->dm.vmax + (1 - fused_parity) * kVmaxSlots;
+                ms.vmax_out = vout;
+            }
+            if (m->dm.av) {
+                if (s == 0)
+                    HIP_TRY(launch_sensor_cfl(m->dm, in[0], eps, vin, st));
+                else
+                    HIP_TRY(launch_sensor(m->dm, in[s], eps, st));
+                HIP_TRY(launch_avgrad(m->dm, in[s], eps, Q, st));
             }
             HIP_TRY(m->time_begin(st));
-            HIP_TRY(launch_stage_mfma(m->dm, in[s], out[s], R, nullptr, s, ms, st));
+            HIP_TRY(launch_stage_mfma(m->dm, in[s], out[s], R, nullptr, s, ms, st, eps, Q));
             HIP_TRY(m->time_end(st));
         }
         return DG_OK;
@@ -536,8 +548,13 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
     HIP_TRY(launch_reset_scalars(m->dm, st));
     HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
     HIP_TRY(hipEventRecord(e0, st));
-    const bool fused = m->dm.fp32 && !m->dm.av;
-    if (fused && nsteps > 0) HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    const bool fused = m->dm.fp32;
+    if (fused && nsteps > 0) {
+        if (m->dm.av)
+            HIP_TRY(hipMemsetAsync(m->dm.vmax, 0, 2 * kVmaxSlots * sizeof(unsigned long long), st));
+        else
+            HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    }
     int done = 0;
     if (fused && m->graphs && !m->timing && nsteps >= 2) {
         if (int rc = ensure_step_graph(m, U, work)) return rc;
@@ -551,6 +568,9 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
         }
     }
     HIP_TRY(hipEventRecord(e1, st));
+    // a fused viscous run checks each step's state in its first sensor: the
+    // final state still needs the check
+    if (fused && m->dm.av && nsteps > 0) HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
     // diagnostics at the end: totals and the residual ||rhs(U)||_inf
     char *w = static_cast<char *>(work);
     void *scratch = w + m->off_A();
@@ -791,9 +811,12 @@ struct Slot {
 struct Group {
     int P = 0;
     bool bf3 = false;
+    bool av = false;               // viscous handles: sensor and gradient records too
     std::vector<int> slots;
     void *jobs = nullptr;
     size_t jobs_cap = 0;
+    void *avjobs = nullptr;        // [parity][stage][job] sensor/gradient records
+    size_t avjobs_cap = 0;
     void *items = nullptr;
     size_t items_cap = 0;
     int nitems = 0;
@@ -805,7 +828,7 @@ struct dg_batch {
     size_t budget = 0, used = 0;
     std::vector<Slot> slots;
     std::vector<Group> groups;
-    std::vector<int> singles;      // slots stepped one by one (FP64 or viscous handles)
+    std::vector<int> singles;      // slots stepped one by one (FP64 handles)
     bool dirty = true;
     long epoch_steps = 0;          // steps since the tables were last built
     hipStream_t cap_stream = nullptr;
@@ -815,6 +838,7 @@ struct dg_batch {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (Group &g : groups) {
             if (g.jobs) (void)hipFree(g.jobs);
+            if (g.avjobs) (void)hipFree(g.avjobs);
             if (g.items) (void)hipFree(g.items);
         }
     }
@@ -822,20 +846,22 @@ struct dg_batch {
 
 namespace {
 
-bool batched_path(const dg_mesh *m) { return m->dm.fp32 && !m->dm.av; }
+bool batched_path(const dg_mesh *m) { return m->dm.fp32; }
 
 // Rebuild the per-order tables for the active, unfinished slots.
 int rebuild(dg_batch *b, hipStream_t st) {
     std::vector<Group> old;
     old.swap(b->groups);
     b->singles.clear();
-    for (int key = 0; key < 10; ++key) {
+    for (int key = 0; key < 20; ++key) {
         Group g;
         g.P = 1 + key % 5;
-        g.bf3 = key >= 5;
+        g.bf3 = (key / 5) & 1;
+        g.av = key >= 10;
         for (size_t i = 0; i < b->slots.size(); ++i) {
             const Slot &s = b->slots[i];
-            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == g.P && s.mesh->dm.bf3 == g.bf3)
+            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == g.P &&
+                s.mesh->dm.bf3 == g.bf3 && s.mesh->dm.av == g.av)
                 g.slots.push_back(int(i));
         }
         if (!g.slots.empty()) b->groups.push_back(std::move(g));
@@ -847,39 +873,49 @@ int rebuild(dg_batch *b, hipStream_t st) {
     // reuse old allocations where they are large enough
     for (Group &g : b->groups) {
         for (Group &o : old)
-            if (o.P == g.P && o.bf3 == g.bf3) {
+            if (o.P == g.P && o.bf3 == g.bf3 && o.av == g.av) {
                 g.jobs = o.jobs;
                 g.jobs_cap = o.jobs_cap;
+                g.avjobs = o.avjobs;
+                g.avjobs_cap = o.avjobs_cap;
                 g.items = o.items;
                 g.items_cap = o.items_cap;
-                o.jobs = o.items = nullptr;
+                o.jobs = o.avjobs = o.items = nullptr;
             }
         const size_t nj = g.slots.size();
-        const size_t rec = mfma_args_bytes();
-        std::vector<char> jobs(2 * 5 * nj * rec);
+        const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
+        std::vector<char> jobs(2 * 5 * nj * rec), avjobs(g.av ? 2 * 5 * nj * arec : 0);
         std::vector<int> items;
         for (size_t j = 0; j < nj; ++j) {
             Slot &s = b->slots[g.slots[j]];
             dg_mesh *m = s.mesh;
             char *w = static_cast<char *>(s.work);
             void *R = w + m->off_R(), *A = w + m->off_A(), *B = w + m->off_B();
+            void *Q = g.av ? w + m->off_Q() : nullptr;
+            void *eps = g.av ? w + m->off_eps() : nullptr;
             void *in[5] = {s.U, A, B, A, B};
             void *out[5] = {A, B, A, B, s.U};
             for (int ps = 0; ps < 2; ++ps) {
                 const int par = (s.parity + ps) & 1;
+                unsigned long long *vin = m->dm.vmax + par * kVmaxSlots;
+                unsigned long long *vout = m->dm.vmax + (1 - par) * kVmaxSlots;
                 for (int st5 = 0; st5 < 5; ++st5) {
+                    // the same time-step handling as a fused single-mesh step
                     MfmaStep ms;
                     if (st5 == 0) {
                         ms.cfl_mode = 1;
-                        ms.vmax_in = m->dm.vmax + par * kVmaxSlots;
-                        ms.vmax_out = m->dm.vmax + (1 - par) * kVmaxSlots;
+                        ms.vmax_in = vin;
+                        ms.vmax_out = vout;
                     }
-                    if (st5 == 4) {
+                    if (st5 == 4 && !g.av) {
                         ms.cfl_accum = 1;
-                        ms.vmax_out = m->dm.vmax + (1 - par) * kVmaxSlots;
+                        ms.vmax_out = vout;
                     }
                     mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms,
-                                   jobs.data() + ((ps * 5 + st5) * nj + j) * rec);
+                                   jobs.data() + ((ps * 5 + st5) * nj + j) * rec, eps, Q);
+                    if (g.av)
+                        av_fill_args(m->dm, in[st5], eps, Q, st5 == 0 ? vin : nullptr,
+                                     avjobs.data() + ((ps * 5 + st5) * nj + j) * arec);
                 }
             }
             const int nt = mfma_tiles(m->dm);
@@ -901,10 +937,15 @@ int rebuild(dg_batch *b, hipStream_t st) {
         if (int rc = grow(&g.jobs, &g.jobs_cap, jobs.size())) return rc;
         if (int rc = grow(&g.items, &g.items_cap, items.size() * sizeof(int))) return rc;
         HIP_TRY(hipMemcpyAsync(g.jobs, jobs.data(), jobs.size(), hipMemcpyHostToDevice, st));
+        if (g.av) {
+            if (int rc = grow(&g.avjobs, &g.avjobs_cap, avjobs.size())) return rc;
+            HIP_TRY(hipMemcpyAsync(g.avjobs, avjobs.data(), avjobs.size(), hipMemcpyHostToDevice, st));
+        }
         HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
     }
     for (Group &o : old) {
         if (o.jobs) (void)hipFree(o.jobs);
+        if (o.avjobs) (void)hipFree(o.avjobs);
         if (o.items) (void)hipFree(o.items);
     }
     if (b->graph) {
@@ -918,11 +959,15 @@ int rebuild(dg_batch *b, hipStream_t st) {
 
 // One lockstep step of every active slot; ps = parity of the epoch step.
 int batch_step(dg_batch *b, int ps, hipStream_t st) {
-    const size_t rec = mfma_args_bytes();
+    const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
     for (int s5 = 0; s5 < 5; ++s5)
         for (const Group &g : b->groups) {
+            if (g.av) {
+                const char *avjobs = static_cast<const char *>(g.avjobs) + (ps * 5 + s5) * g.slots.size() * arec;
+                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.nitems, st));
+            }
             const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * g.slots.size() * rec;
-            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, jobs, g.items, g.nitems, st));
+            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, jobs, g.items, g.nitems, st));
         }
     for (int i : b->singles) {
         Slot &s = b->slots[i];
@@ -972,7 +1017,12 @@ int dg_batch_admit(dg_batch *b, dg_mesh *m, void *U, void *work, int nsteps, voi
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_reset_scalars(m->dm, st));
     HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
-    if (batched_path(m)) HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    if (batched_path(m)) {
+        if (m->dm.av)
+            HIP_TRY(hipMemsetAsync(m->dm.vmax, 0, 2 * kVmaxSlots * sizeof(unsigned long long), st));
+        else
+            HIP_TRY(launch_cfl_vmax(m->dm, U, m->dm.vmax, st));
+    }
     Slot &s = b->slots[free_slot];
     s = Slot();
     s.used = true;

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstring>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -47,16 +48,18 @@ struct Tile {
     int lane, wave, le, i, el;
     long k;
     bool act;
-    __device__ Tile(int K) {
+    // tile `tile` of a mesh of K elements (a single-mesh launch: the block index)
+    __device__ Tile(int K, int tile) {
         lane = threadIdx.x & 63;
         wave = threadIdx.x >> 6;
         le = lane / O::Np;
         i = lane - le * O::Np;
         bool lane_ok = le < O::EW;
         el = lane_ok ? wave * O::EW + le : 0;
-        k = (long)blockIdx.x * O::EB + wave * O::EW + le;
+        k = (long)tile * O::EB + wave * O::EW + le;
         act = lane_ok && k < K;
     }
+    __device__ explicit Tile(int K) : Tile(K, blockIdx.x) {}
 };
 
 template <typename T, int P, bool AV>
@@ -198,18 +201,25 @@ struct AvArgs {
     const T *__restrict__ fgeo;
     const T *__restrict__ ops;
     const T *__restrict__ emax;
+    unsigned long long *__restrict__ vmax;   // CFL-bound slots (sensor with the bound only)
+    int *__restrict__ flag;                  // state check (sensor with the bound only)
 };
 
 // Persson-Peraire sensor on the density: u_hat = V^{-1} rho, S = (energy of
 // the degree-P modes) / (total modal energy), s = log10 S, sine ramp of
-// half-width kappa around s0, capped at eps_max,k.
-template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
+// half-width kappa around s0, capped at eps_max,k.  CFL: also the time-step
+// bound of the state with its new viscosity (FP32 arithmetic per face node,
+// like the stage kernel's fused bound), reduced into the block's slot, and
+// the state check (rho, p > 0, finite).
+template <typename T, int P, bool CFL>
+__device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) {
     using O = Order<P>;
-    constexpr int Np = O::Np, Nfp = O::Nfp, EB = O::EB;
+    constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
     __shared__ T sR[EB][Np];
     __shared__ double sE[EB][Np];
-    Tile<P> t(a.K);
+    __shared__ T sEps[EB];
+    __shared__ float sRed[kBlock / 64];
+    Tile<P> t(a.K, tile);
     if (t.act) sR[t.el][t.i] = a.U[(t.k * kFields + 0) * Np + t.i];
     __syncthreads();
     if (t.act) {
@@ -236,20 +246,68 @@ __global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
                 e = 0.5 * emax * (1.0 + sin(M_PI * (sk - a.s0) / (2.0 * a.kappa)));
         }
         a.eps_out[t.k] = T(e);
+        if constexpr (CFL) sEps[t.el] = T(e);
     }
+    if constexpr (CFL) {
+        __syncthreads();
+        float vmax = 0.f;
+        int bad = 0;
+        if (t.act) {
+            const T *Uk = a.U + t.k * kFields * Np;
+            {
+                T u[kFields];
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) u[c] = Uk[c * Np + t.i];
+                const T p = pressure(a.g, u);
+                if (!(u[0] > T(0)) || !(p > T(0)) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+                    !isfinite(p))
+                    bad = 1;
+            }
+            const float P1 = P + 1.0f, e = float(sEps[t.el]);
+            for (int q = t.i; q < NF3; q += Np) {
+                const int v = face_node(P, q / Nfp, q % Nfp);
+                float u[kFields];
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) u[c] = float(Uk[c * Np + v]);
+                const float ir = 1.0f / u[0];
+                const float vx = u[1] * ir, vy = u[2] * ir;
+                const float p = pressure(float(a.g), u);
+                const float lam = sqrtf(vx * vx + vy * vy) + sqrtf(float(a.g) * p * ir);
+                const float fs = float(a.fgeo[(t.k * 3 + 2) * NF3 + q]);
+                const float val = 0.5f * P1 * P1 * fs * lam + 0.25f * P1 * P1 * P1 * P1 * fs * fs * e;
+                vmax = fmaxf(vmax, val);
+            }
+        }
+        if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.flag, 1);
+        for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+        if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = vmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = sRed[0];
+            for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sRed[w]);
+            // non-negative doubles order like their bit patterns
+            atomicMax(a.vmax + (blockIdx.x & (kVmaxSlots - 1)),
+                      (unsigned long long)__double_as_longlong(double(m)));
+        }
+    }
+}
+
+template <typename T, int P, bool CFL>
+__global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
+    sensor_body<T, P, CFL>(a, blockIdx.x);
 }
 
 // Auxiliary variable of the viscous system, q = sigma grad U (sigma =
 // sqrt eps_k), strong form with the central trace (sigma U)*:
 //   Q_x = sigma (r_x Dr U + s_x Ds U) + LIFT [Fscale n_x ((sigma U)* - sigma U-)]
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
+__device__ __forceinline__ void avgrad_body(const AvArgs<T> &a, const int tile) {
     using O = Order<P>;
     constexpr int Np = O::Np, Nfp = O::Nfp, NF3 = O::Nface, EB = O::EB;
     __shared__ T sU[EB][kFields][Np];
     __shared__ T sX[EB][kFields][NF3];
     __shared__ T sY[EB][kFields][NF3];
-    Tile<P> t(a.K);
+    Tile<P> t(a.K, tile);
     const long k = t.k;
     const int i = t.i, el = t.el;
     T sig = 0;
@@ -314,6 +372,29 @@ __global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
         a.Q[((k * 2 + 0) * kFields + c) * Np + i] = qx;
         a.Q[((k * 2 + 1) * kFields + c) * Np + i] = qy;
     }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
+    avgrad_body<T, P>(a, blockIdx.x);
+}
+
+// Batched meshes of one order (FP32 viscous handles): work item = (job,
+// tile), a job being one mesh's argument record for this stage.
+template <int P, bool CFL>
+__global__ __launch_bounds__(kBlock) void k_sensor_batch(const AvArgs<float> *__restrict__ jobs,
+                                                         const int2 *__restrict__ items, int nitems) {
+    if ((int)blockIdx.x >= nitems) return;
+    const int2 it = items[blockIdx.x];
+    sensor_body<float, P, CFL>(jobs[it.x], it.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_avgrad_batch(const AvArgs<float> *__restrict__ jobs,
+                                                         const int2 *__restrict__ items, int nitems) {
+    if ((int)blockIdx.x >= nitems) return;
+    const int2 it = items[blockIdx.x];
+    avgrad_body<float, P>(jobs[it.x], it.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -742,6 +823,8 @@ AvArgs<T> av_args(const DevMesh &m) {
     a.fgeo = tbl_fgeo<T>(m);
     a.ops = tbl_ops<T>(m);
     a.emax = tbl_emax<T>(m);
+    a.vmax = nullptr;
+    a.flag = m.flag;
     return a;
 }
 
@@ -804,19 +887,59 @@ hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, 
 }
 
 template <typename T>
-static hipError_t sensor_t(const DevMesh &m, const void *U, void *eps, hipStream_t st) {
+static hipError_t sensor_t(const DevMesh &m, const void *U, void *eps, unsigned long long *vmax,
+                           hipStream_t st) {
     AvArgs<T> a = av_args<T>(m);
     a.U = static_cast<const T *>(U);
     a.eps_out = static_cast<T *>(eps);
+    a.vmax = vmax;
     return with_order(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        hipLaunchKernelGGL((k_sensor<T, P>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        if (vmax)
+            hipLaunchKernelGGL((k_sensor<T, P, true>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sensor<T, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_sensor(const DevMesh &m, const void *U, void *eps, hipStream_t st) {
-    return m.fp32 ? sensor_t<float>(m, U, eps, st) : sensor_t<double>(m, U, eps, st);
+    return m.fp32 ? sensor_t<float>(m, U, eps, nullptr, st) : sensor_t<double>(m, U, eps, nullptr, st);
+}
+
+hipError_t launch_sensor_cfl(const DevMesh &m, const void *U, void *eps, unsigned long long *vmax,
+                             hipStream_t st) {
+    if (!m.fp32) return hipErrorInvalidValue;
+    return sensor_t<float>(m, U, eps, vmax, st);
+}
+
+size_t av_args_bytes() { return sizeof(AvArgs<float>); }
+
+void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned long long *vmax, void *out) {
+    AvArgs<float> a = av_args<float>(m);
+    a.U = static_cast<const float *>(U);
+    a.eps_out = static_cast<float *>(eps);
+    a.eps_in = static_cast<const float *>(eps);
+    a.Q = static_cast<float *>(Q);
+    a.vmax = vmax;
+    std::memcpy(out, &a, sizeof(a));
+}
+
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const auto *j = static_cast<const AvArgs<float> *>(jobs);
+    const auto *it = static_cast<const int2 *>(items);
+    return with_order(P, [&](auto PC) {
+        constexpr int PP = decltype(PC)::value;
+        if (cfl)
+            hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
+        else
+            hipLaunchKernelGGL((k_sensor_batch<PP, false>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>

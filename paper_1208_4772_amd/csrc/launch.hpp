@@ -102,9 +102,9 @@ int mfma_curved_bit();
 // work list of (record, tile) items, all meshes of order P
 size_t mfma_args_bytes();
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
-                    void *out);
+                    void *out, const void *eps = nullptr, const void *Q = nullptr);
 int mfma_tiles(const DevMesh &m);
-hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void *items, int nitems,
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items, int nitems,
                                    hipStream_t st);
 // CFL bound of state U (FP64) into *slot as a bit pattern; raises *flag on bad states
 hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st);
@@ -123,8 +123,20 @@ hipError_t launch_pack_geometry(const DevMesh &m, const int *cidx, float *geoA, 
 
 // sensor: eps [K] (state precision) from U
 hipError_t launch_sensor(const DevMesh &m, const void *U, void *eps, hipStream_t st);
+// FP32 handles: the sensor plus the CFL bound of U with its new viscosity
+// (FP32 per face node) reduced into the slots vmax[kVmaxSlots] (which must
+// hold zeros or smaller bounds), and the state check into *flag
+hipError_t launch_sensor_cfl(const DevMesh &m, const void *U, void *eps, unsigned long long *vmax,
+                             hipStream_t st);
 // LDG auxiliary gradient Q from U and eps
 hipError_t launch_avgrad(const DevMesh &m, const void *U, const void *eps, void *Q, hipStream_t st);
+// batched FP32 viscous handles of order P: per-(mesh, stage) argument
+// records and the (record, tile) work list of the stage kernel's batch;
+// one launch of the sensor (with the CFL bound when cfl) and one of the
+// gradient over all of them
+size_t av_args_bytes();
+void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned long long *vmax, void *out);
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems, hipStream_t st);
 // CFL reduction -> scal[S_DT] (dt_fixed > 0 overrides), accumulates S_T,
 // S_DTMIN/MAX, S_STEPS; raises *flag on bad states.
 hipError_t launch_cfl(const DevMesh &m, const void *U, const void *eps, double dt_fixed,

@@ -583,14 +583,14 @@ void k_stage_mfma(MfmaArgs a) {
 
 // Batched meshes of one order: work item = (job, tile); a job is one mesh's
 // argument record for this stage.
-template <int P, bool BF3, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W>())))
+template <int P, bool BF3, int W, bool AV>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W, AV>())))
 void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restrict__ items, int nitems,
                         int chunk) {
     const int w = xcd_item(chunk);
     if (w >= nitems) return;
     const int2 it = items[w];
-    stage_tile<P, BF3, W, false>(jobs[it.x], it.y);
+    stage_tile<P, BF3, W, AV>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -766,8 +766,8 @@ size_t mfma_args_bytes() { return sizeof(MfmaArgs); }
 
 // Batches use the default workgroup shape of their order.
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
-                    void *out) {
-    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, default_waves(m.P));
+                    void *out, const void *eps, const void *Q) {
+    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, default_waves(m.P), eps, Q);
     std::memcpy(out, &a, sizeof(a));
 }
 
@@ -776,22 +776,24 @@ int mfma_tiles(const DevMesh &m) {
     return (m.K + eb - 1) / eb;
 }
 
-hipError_t launch_stage_mfma_batch(int P, bool bf3, const void *jobs, const void *items, int nitems,
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items, int nitems,
                                    hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const int chunk = (nitems + 7) / 8;
+    const auto *j = static_cast<const MfmaArgs *>(jobs);
+    const auto *it = static_cast<const int2 *>(items);
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
-        if (bf3)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, default_waves(PP)>), dim3(8 * chunk),
-                               dim3(64 * default_waves(PP)), 0,
-                               st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
-                               nitems, chunk);
+        constexpr int W = default_waves(PP);
+        const dim3 grid(8 * chunk), block(64 * W);
+        if (bf3 && av)
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, true>), grid, block, 0, st, j, it, nitems, chunk);
+        else if (bf3)
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, false>), grid, block, 0, st, j, it, nitems, chunk);
+        else if (av)
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, true>), grid, block, 0, st, j, it, nitems, chunk);
         else
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, default_waves(PP)>), dim3(8 * chunk),
-                               dim3(64 * default_waves(PP)), 0,
-                               st, static_cast<const MfmaArgs *>(jobs), static_cast<const int2 *>(items),
-                               nitems, chunk);
+            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, false>), grid, block, 0, st, j, it, nitems, chunk);
         return hipGetLastError();
     });
 }
