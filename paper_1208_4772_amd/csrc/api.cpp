@@ -1092,6 +1092,10 @@ int dg_batch_advance(dg_batch *b, int max_steps, void *stream, int *steps_run) {
             if (s.remaining == 0) {
                 s.finished = true;
                 b->dirty = true;
+                // a batched viscous slot checks each step's state in that
+                // step's first sensor: check the final state as dg_run does
+                if (batched_path(s.mesh) && s.mesh->dm.av)
+                    HIP_TRY(launch_cfl_vmax(s.mesh->dm, s.U, s.mesh->dm.vmax, st));
             }
         }
     if (steps_run) *steps_run = n;
