@@ -154,7 +154,11 @@ int dg_step(dg_mesh *mesh, void *U, void *work, double dt, void *stream);
 
 /* nsteps CFL steps of U in place, then totals and residual; synchronises
  * and fills *stats (may be NULL).  Returns DG_ENONFINITE if the state
- * became non-finite, rho <= 0 or p <= 0 at any step. */
+ * became non-finite, rho <= 0 or p <= 0 at any step.  FP32 handles take
+ * the CFL bound from the stage kernels themselves (without viscosity: the
+ * last stage, for the next step; with viscosity: the first stage's sensor),
+ * in FP32 per face node with dt formed in FP64; FP64 handles and dg_step
+ * use the FP64 reduction. */
 int dg_run(dg_mesh *mesh, void *U, void *work, int nsteps, dg_run_stats *stats, void *stream);
 
 /* Conserved totals sum_k sum_i w_ki U_ki, w_ki = sum_j M_ij J_kj, in FP64
@@ -170,10 +174,10 @@ int dg_residual(dg_mesh *mesh, const void *U, void *work, double out[4], void *s
 int dg_viscosity(dg_mesh *mesh, const void *U, double *eps, void *stream);
 
 /* Replay of captured steps.  With graphs enabled (the default), dg_run on
- * an FP32 handle without artificial viscosity captures two steps into a
- * hipGraph once per (U, work) pair and replays it, which removes per-launch
- * host overhead; the arithmetic is identical to the eager launches.  Graphs
- * are not used while kernel timing is enabled. */
+ * an FP32 handle (with or without artificial viscosity) captures two steps
+ * into a hipGraph once per (U, work) pair and replays it, which removes
+ * per-launch host overhead; the arithmetic is identical to the eager
+ * launches.  Graphs are not used while kernel timing is enabled. */
 int dg_set_graphs(dg_mesh *mesh, int enable);
 
 /* Per-launch timing of the fused stage kernel.  With timing enabled,

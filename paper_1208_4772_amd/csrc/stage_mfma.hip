@@ -24,10 +24,11 @@
 // (the result is staged in the B operand's own space) so that several
 // blocks share a CU and hide each other's memory latency.
 //
-// Time step: in a fused run the last stage also reduces the CFL bound of
-// the new state (FP64 arithmetic) into a device slot, and the next step's
-// first stage turns it into dt, so a step needs no separate reduction
-// launches.
+// Time step: in a fused run without viscosity the last stage also reduces
+// the CFL bound of the new state (FP32 per node, exact maximum) into
+// device slots, and the next step's first stage turns it into dt (FP64), so
+// a step needs no separate reduction launches; with viscosity the first
+// stage's sensor fills the slots instead (it knows the new viscosity).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
