@@ -7,7 +7,8 @@ from .meshes import (BC_FARFIELD, BC_INTERIOR, BC_WALL, FACE_VERTS, Mesh,  # noq
                      connect, cylinder_annulus, naca4_ogrid, naca4_thickness,
                      naca_point, node_coordinates, periodic_square,
                      permute_elements)
-from .flows import (GAMMA, cylinder_potential, freestream_state,  # noqa: F401
+from .flows import (GAMMA, airfoil_panels, airfoil_potential, airfoil_velocity,  # noqa: F401
+                    cylinder_potential, freestream_state,
                     isentropic_vortex, primitive_to_conserved, uniform,
                     wall_damped)
 from .cases import CASES, make_case  # noqa: F401

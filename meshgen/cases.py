@@ -63,8 +63,9 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
               start: str = "freestream") -> Case:
     """Build one of ``CASES``.  ``scale`` < 1 shrinks the element count.
     ``start`` for the cylinder and the airfoil: "freestream" (impulsive),
-    "potential" (cylinder only: the wall-compatible potential flow) or
-    "damped" (the freestream with its velocity damped to rest at the wall)."""
+    "potential" (the wall-compatible potential flow: closed form for the
+    cylinder, a panel solution for the airfoil) or "damped" (the freestream
+    with its velocity damped to rest at the wall)."""
     r = np.asarray(r, dtype=np.float64)
     s = np.asarray(s, dtype=np.float64)
     if name == "vortex":
@@ -104,6 +105,8 @@ def make_case(name: str, r, s, scale: float = 1.0, P: int | None = None,
         q = flows.freestream_state(M, 1.25)
         if start == "damped":
             U0 = flows.wall_damped(x, y, *_wall_points(mesh), q)
+        elif start == "potential":
+            U0 = flows.airfoil_potential(x, y, M, 1.25)
         elif start == "freestream":
             U0 = flows.uniform((mesh.K, x.shape[1]), q)
         else:

@@ -144,4 +144,44 @@ def test_wall_damped_start():
     np.testing.assert_allclose(u[far], q[1], rtol=1e-12)
     np.testing.assert_allclose(v[far], q[2], rtol=1e-12)
     with pytest.raises(ValueError):
-        meshgen.make_case("airfoil", r, s, scale=0.01, start="potential")
+        meshgen.make_case("airfoil", r, s, scale=0.01, start="nonsense")
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.25, 4.0])
+def test_airfoil_panel_solution(alpha):
+    """Zero normal velocity at the panel midpoints, the freestream far away,
+    lift from the circulation (Kutta-Joukowski) within 2% of thin-airfoil
+    theory with the thickness correction, 2 pi alpha (1 + 0.77 t), and
+    no lift at zero incidence."""
+    import math
+    panels, q, g, Vinf = meshgen.airfoil_panels(0.8, alpha)
+    ax, ay, bx, by = panels
+    L = np.hypot(bx - ax, by - ay)
+    nx, ny = (by - ay) / L, -(bx - ax) / L
+    u, v = meshgen.airfoil_velocity(0.5 * (ax + bx) + 1e-9 * nx, 0.5 * (ay + by) + 1e-9 * ny, panels, q, g, Vinf,
+                                    standoff=0.0)
+    assert np.abs(u * nx + v * ny).max() < 1e-6
+    uf, vf = meshgen.airfoil_velocity(np.array([3e4]), np.array([-2e4]), panels, q, g, Vinf)
+    np.testing.assert_allclose([uf[0], vf[0]], Vinf, atol=1e-4)
+    CL = -2 * g * L.sum() / math.hypot(*Vinf)
+    thin = 2 * math.pi * math.radians(alpha) * (1 + 0.77 * 0.12)
+    if alpha == 0.0:
+        assert abs(CL) < 1e-10
+    else:
+        assert abs(CL / thin - 1) < 0.02, (CL, thin)
+
+
+def test_airfoil_potential_start():
+    """Freestream far away; constant total enthalpy; the airfoil case's
+    potential start is that state at the mesh nodes."""
+    x = np.array([0.5, -0.3, 2.0, 40.0])
+    y = np.array([0.2, 0.05, -0.4, 30.0])
+    U = meshgen.airfoil_potential(x, y, 0.6, 1.25)
+    rho, u, v = U[0], U[1] / U[0], U[2] / U[0]
+    p = 0.4 * (U[3] - 0.5 * rho * (u * u + v * v))
+    H = 1.4 * p / rho / 0.4 + 0.5 * (u * u + v * v)
+    np.testing.assert_allclose(H, 1 / 0.4 + 0.18, rtol=1e-13)
+    np.testing.assert_allclose(U[:, -1], meshgen.freestream_state(0.6, 1.25), rtol=1e-3, atol=1e-3)
+    r, s = np.array([-1.0, 1.0, -1.0]), np.array([-1.0, -1.0, 1.0])
+    case = meshgen.make_case("airfoil", r, s, scale=0.01, start="potential", mach=0.6)
+    np.testing.assert_allclose(case.U0, meshgen.airfoil_potential(case.x, case.y, 0.6, 1.25), rtol=0, atol=0)
