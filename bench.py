@@ -78,7 +78,39 @@ def algorithmic_stage_bytes(case, s):
     traces = interior_sides * Nfp * 4 * s
     geom = (K - curved) * 13 * s + curved * (4 * Np + 9 * Nfp) * s
     conn = 12 * K
-    return state + traces + geom + conn, dict(curved=curved, interior_sides=interior_sides)
+    total = state + traces + geom + conn
+    if case.av:
+        # the viscous terms add two launches per stage.  Sensor: density and
+        # the element's viscosity ceiling in, viscosity out (the first stage
+        # of a step also reads the rest of the state and the face Fscale for
+        # the time-step bound).  Gradient: state, viscosity, per-node metrics
+        # and face geometry (4 Np + 9 Nfp values) and 16 bytes of
+        # connectivity in, the neighbours' state traces and viscosity,
+        # sigma grad U (8 Np values) out.  Stage: sigma grad U and the
+        # viscosity in, the neighbours' traces of it (8 values per face
+        # node) and their viscosity.
+        sensor = K * (Np * s + 2 * s) + K * (3 * Np + 3 * Nfp) * s / 5
+        grad = (K * ((4 * Np + 1 + 8 * Np + 4 * Np + 9 * Nfp) * s + 16)
+                + interior_sides * (Nfp * 4 * s + s))
+        stage_av = K * (8 * Np * s + s) + interior_sides * (Nfp * 8 * s + s)
+        total += sensor + grad + stage_av
+    return total, dict(curved=curved, interior_sides=interior_sides)
+
+
+def stage_kernel_label(case, precision, waves):
+    """The launch(es) one Runge-Kutta stage consists of: the stage kernel, and
+    with artificial viscosity the sensor and gradient launches before it
+    (their time is in the per-stage average, so their bytes are in the
+    algorithmic figure)."""
+    av = "true" if case.av else "false"
+    if precision == "fp64":
+        k = f"k_stage<double,{case.P},{av}>"
+    else:
+        k = (f"k_stage_mfma<{case.P},{'true' if precision == 'bf16x3' else 'false'},"
+             f"{waves or 4},{av}>")
+    if case.av:
+        return f"k_sensor<{case.P}> + k_avgrad<{case.P}> + {k}"
+    return k
 
 
 def load_traffic(workload, precision, launch_bytes):
@@ -216,9 +248,7 @@ def main():
     traffic = load_traffic(args.workload, args.precision, launch_bytes)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=(f"k_stage<double,{case.P},false>" if args.precision == "fp64" else
-                            f"k_stage_mfma<{case.P},{'true' if args.precision == 'bf16x3' else 'false'},"
-                            f"{tuned.get(args.precision, (0, 0.0))[0] or 4},false>"),
+                    kernel=stage_kernel_label(case, args.precision, tuned.get(args.precision, (0, 0.0))[0]),
                     avg_launch_us=round(avg_s * 1e6, 3),
                     launches=5 * steps,
                     waves_per_block=tuned.get(args.precision, (0, 0.0))[0] or None,
