@@ -219,13 +219,17 @@ __device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) 
     __shared__ double sE[EB][Np];
     __shared__ T sEps[EB];
     __shared__ float sRed[kBlock / 64];
+    // V^{-1} staged once per block: every thread reads a row of it, and
+    // reading it through the caches costs a memory instruction per entry
+    __shared__ T sVi[Np * Np];
+    for (int z = threadIdx.x; z < Np * Np; z += kBlock) sVi[z] = a.ops[(2 * Np * Np + Np * 3 * Nfp) + z];
     Tile<P> t(a.K, tile);
     if (t.act) sR[t.el][t.i] = a.U[(t.k * kFields + 0) * Np + t.i];
     __syncthreads();
     if (t.act) {
         T uh = 0;
 #pragma unroll
-        for (int j = 0; j < Np; ++j) uh += a.ops[(2 * Np * Np + Np * 3 * Nfp) + t.i * Np + j] * sR[t.el][j];
+        for (int j = 0; j < Np; ++j) uh += sVi[t.i * Np + j] * sR[t.el][j];
         sE[t.el][t.i] = double(uh) * double(uh);
     }
     __syncthreads();
@@ -307,6 +311,12 @@ __device__ __forceinline__ void avgrad_body(const AvArgs<T> &a, const int tile) 
     __shared__ T sU[EB][kFields][Np];
     __shared__ T sX[EB][kFields][NF3];
     __shared__ T sY[EB][kFields][NF3];
+    // Dr, Ds and LIFT staged once per block (the same values in the same
+    // order as from global memory, so the results do not change; the block
+    // then reads them from LDS instead of issuing a cached load per entry)
+    constexpr int NOPS = 2 * Np * Np + Np * NF3;
+    __shared__ T sOps[NOPS];
+    for (int z = threadIdx.x; z < NOPS; z += kBlock) sOps[z] = a.ops[z];
     Tile<P> t(a.K, tile);
     const long k = t.k;
     const int i = t.i, el = t.el;
@@ -358,14 +368,14 @@ __device__ __forceinline__ void avgrad_body(const AvArgs<T> &a, const int tile) 
 #pragma unroll
         for (int j = 0; j < Np; ++j) {
             const T uv = sU[el][c][j];
-            dru += a.ops[i * Np + j] * uv;
-            dsu += a.ops[Np * Np + i * Np + j] * uv;
+            dru += sOps[i * Np + j] * uv;
+            dsu += sOps[Np * Np + i * Np + j] * uv;
         }
         T qx = sig * (rx * dru + sx * dsu);
         T qy = sig * (ry * dru + sy * dsu);
 #pragma unroll
         for (int q = 0; q < NF3; ++q) {
-            const T l = a.ops[2 * Np * Np + i * NF3 + q];
+            const T l = sOps[2 * Np * Np + i * NF3 + q];
             qx += l * sX[el][c][q];
             qy += l * sY[el][c][q];
         }
