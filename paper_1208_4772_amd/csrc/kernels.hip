@@ -69,6 +69,12 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     __shared__ T sU[EB][kFields][Np];
     __shared__ T sF[EB][2 * kFields][Np];
     __shared__ T sJ[EB][kFields][NF3];
+    // Dr, Ds and LIFT staged once per block; every thread needs its node's
+    // rows of them, which through the caches cost a memory instruction per
+    // entry
+    constexpr int NOPS = 2 * Np * Np + Np * NF3;
+    __shared__ T sOps[NOPS];
+    for (int z = threadIdx.x; z < NOPS; z += kBlock) sOps[z] = a.ops[z];
     Tile<P> t(a.K);
     const long k = t.k;
     const int i = t.i, el = t.el;
@@ -145,14 +151,30 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     __syncthreads();
     if (!t.act) return;
 
-    T dr[Np], ds[Np], lf[NF3];
+    // the node's operator rows: copied into registers up to P = 4; at P = 5
+    // (60 values) read from LDS inside the contraction, which leaves the
+    // registers for more resident waves (faster there, slower below; the
+    // values and the order of operations are the same either way)
+    constexpr bool kRowsInRegs = P < 5;
+    T rdr[kRowsInRegs ? Np : 1], rds[kRowsInRegs ? Np : 1], rlf[kRowsInRegs ? NF3 : 1];
+    if constexpr (kRowsInRegs) {
 #pragma unroll
-    for (int j = 0; j < Np; ++j) {
-        dr[j] = a.ops[i * Np + j];
-        ds[j] = a.ops[Np * Np + i * Np + j];
+        for (int j = 0; j < Np; ++j) {
+            rdr[j] = sOps[i * Np + j];
+            rds[j] = sOps[Np * Np + i * Np + j];
+        }
+#pragma unroll
+        for (int q = 0; q < NF3; ++q) rlf[q] = sOps[2 * Np * Np + i * NF3 + q];
     }
-#pragma unroll
-    for (int q = 0; q < NF3; ++q) lf[q] = a.ops[2 * Np * Np + i * NF3 + q];
+    auto dr = [&](int j) -> T {
+        if constexpr (kRowsInRegs) return rdr[j]; else return sOps[i * Np + j];
+    };
+    auto ds = [&](int j) -> T {
+        if constexpr (kRowsInRegs) return rds[j]; else return sOps[Np * Np + i * Np + j];
+    };
+    auto lf = [&](int q) -> T {
+        if constexpr (kRowsInRegs) return rlf[q]; else return sOps[2 * Np * Np + i * NF3 + q];
+    };
     const T rx = a.geo[(k * 4 + 0) * Np + i], sx = a.geo[(k * 4 + 1) * Np + i];
     const T ry = a.geo[(k * 4 + 2) * Np + i], sy = a.geo[(k * 4 + 3) * Np + i];
     const T dt = a.mode ? T(*a.dt) : T(0);
@@ -162,14 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
 #pragma unroll
         for (int j = 0; j < Np; ++j) {
             const T fv = sF[el][c][j], gv = sF[el][kFields + c][j];
-            drf += dr[j] * fv;
-            dsf += ds[j] * fv;
-            drg += dr[j] * gv;
-            dsg += ds[j] * gv;
+            drf += dr(j) * fv;
+            dsf += ds(j) * fv;
+            drg += dr(j) * gv;
+            dsg += ds(j) * gv;
         }
         T val = -(rx * drf + sx * dsf + ry * drg + sy * dsg);
 #pragma unroll
-        for (int q = 0; q < NF3; ++q) val += lf[q] * sJ[el][c][q];
+        for (int q = 0; q < NF3; ++q) val += lf(q) * sJ[el][c][q];
         const long idx = (k * kFields + c) * Np + i;
         if (a.mode == 0) {
             a.rhs[idx] = val;
