@@ -62,6 +62,27 @@ struct Tile {
     __device__ explicit Tile(int K) : Tile(K, blockIdx.x) {}
 };
 
+// A block-wide copy of N values into LDS in two halves: load() issues each
+// thread's loads back to back (indices clamped, no branches) and store()
+// writes them to LDS later, after the kernel has issued its own loads, so
+// that the copy's latency overlaps theirs instead of preceding them.
+template <typename T, int N>
+struct LdsCopy {
+    static constexpr int R = (N + kBlock - 1) / kBlock;
+    T v[R];
+    __device__ void load(const T *__restrict__ src) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[min(int(threadIdx.x) + r * kBlock, N - 1)];
+    }
+    __device__ void store(T *dst) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int z = int(threadIdx.x) + r * kBlock;
+            if (z < N) dst[z] = v[r];
+        }
+    }
+};
+
 template <typename T, int P, bool AV>
 __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     using O = Order<P>;
@@ -74,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     // entry
     constexpr int NOPS = 2 * Np * Np + Np * NF3;
     __shared__ T sOps[NOPS];
-    for (int z = threadIdx.x; z < NOPS; z += kBlock) sOps[z] = a.ops[z];
+    LdsCopy<T, NOPS> opsc;
+    opsc.load(a.ops);
     Tile<P> t(a.K);
     const long k = t.k;
     const int i = t.i, el = t.el;
@@ -104,6 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
             sF[el][kFields + c][i] = G[c];
         }
     }
+    opsc.store(sOps);
     __syncthreads();
 
     if (t.act) {
@@ -244,9 +267,11 @@ __device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) 
     // V^{-1} staged once per block: every thread reads a row of it, and
     // reading it through the caches costs a memory instruction per entry
     __shared__ T sVi[Np * Np];
-    for (int z = threadIdx.x; z < Np * Np; z += kBlock) sVi[z] = a.ops[(2 * Np * Np + Np * 3 * Nfp) + z];
+    LdsCopy<T, Np * Np> vic;
+    vic.load(a.ops + (2 * Np * Np + Np * 3 * Nfp));
     Tile<P> t(a.K, tile);
     if (t.act) sR[t.el][t.i] = a.U[(t.k * kFields + 0) * Np + t.i];
+    vic.store(sVi);
     __syncthreads();
     if (t.act) {
         T uh = 0;
@@ -338,7 +363,8 @@ __device__ __forceinline__ void avgrad_body(const AvArgs<T> &a, const int tile) 
     // then reads them from LDS instead of issuing a cached load per entry)
     constexpr int NOPS = 2 * Np * Np + Np * NF3;
     __shared__ T sOps[NOPS];
-    for (int z = threadIdx.x; z < NOPS; z += kBlock) sOps[z] = a.ops[z];
+    LdsCopy<T, NOPS> opsc;
+    opsc.load(a.ops);
     Tile<P> t(a.K, tile);
     const long k = t.k;
     const int i = t.i, el = t.el;
@@ -348,6 +374,7 @@ __device__ __forceinline__ void avgrad_body(const AvArgs<T> &a, const int tile) 
 #pragma unroll
         for (int c = 0; c < kFields; ++c) sU[el][c][i] = a.U[(k * kFields + c) * Np + i];
     }
+    opsc.store(sOps);
     __syncthreads();
     if (t.act) {
         const int info = a.finfo[k];
