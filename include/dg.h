@@ -57,7 +57,7 @@ enum dg_status {
     DG_EGEOM = -3,       /* J <= 0 at some node, or mismatched face normals */
     DG_ENONFINITE = -4,  /* state became non-finite or rho <= 0 or p <= 0 */
     DG_EDEVICE = -5,     /* HIP runtime error */
-    DG_EBUSY = -6        /* resource exhausted (reserved) */
+    DG_EBUSY = -6        /* batch admission: no free slot, or over the HBM budget */
 };
 
 enum dg_precision {
