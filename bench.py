@@ -48,10 +48,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(precision="fp32"):
-    """Hash of the sources of the dominant stage kernel for this precision."""
+def kernel_source_hash(precision="fp32", av=False):
+    """Hash of the sources of the stage's kernels for this precision (with
+    artificial viscosity the sensor and gradient kernels too)."""
     h = hashlib.sha256()
     files = ("kernels.hip", "common.hpp") if precision == "fp64" else ("stage_mfma.hip", "common.hpp")
+    if av and precision != "fp64":
+        files += ("kernels.hip",)
     for f in files:
         with open(os.path.join(ROOT, "paper_1208_4772_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -113,15 +116,16 @@ def stage_kernel_label(case, precision, waves):
     return k
 
 
-def load_traffic(workload, precision, launch_bytes):
-    """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (else None)."""
+def load_traffic(workload, precision, launch_bytes, av=False):
+    """HBM traffic per launch (per stage, with artificial viscosity) from
+    committed rocprofv3 counter runs, if they were taken on the current
+    kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_stage_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash(precision):
+    if t.get("kernel_source_hash") != kernel_source_hash(precision, av):
         return None
     return t.get("bytes_per_launch")
 
@@ -245,7 +249,7 @@ def main():
     sbytes = 8 if args.precision == "fp64" else 4
     launch_bytes, geo_info = algorithmic_stage_bytes(case, sbytes)
     achieved = launch_bytes / avg_s / 1e9
-    traffic = load_traffic(args.workload, args.precision, launch_bytes)
+    traffic = load_traffic(args.workload, args.precision, launch_bytes, case.av)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=stage_kernel_label(case, args.precision, tuned.get(args.precision, (0, 0.0))[0]),
