@@ -1,4 +1,4 @@
-"""Python driver of the FP64 CPU oracle (``dg_oracle.c``).
+"""Python front end of the FP64 CPU oracle (``dg_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the solver.  It builds the C core with
