@@ -104,7 +104,8 @@ def stage_kernel_label(case, precision, waves):
     """The launch(es) one Runge-Kutta stage consists of: the stage kernel, and
     with artificial viscosity the sensor and gradient launches before it
     (their time is in the per-stage average, so their bytes are in the
-    algorithmic figure)."""
+    algorithmic figure; a step's first stage runs the sensor that also
+    reduces the time-step bound, k_sensor, in place of k_sensor_elem)."""
     av = "true" if case.av else "false"
     if precision == "fp64":
         k = f"k_stage<double,{case.P},{av}>"
@@ -112,7 +113,7 @@ def stage_kernel_label(case, precision, waves):
         k = (f"k_stage_mfma<{case.P},{'true' if precision == 'bf16x3' else 'false'},"
              f"{waves or 4},{av}>")
     if case.av:
-        return f"k_sensor<{case.P}> + k_avgrad<{case.P}> + {k}"
+        return f"k_sensor_elem<{case.P}> + k_avgrad<{case.P}> + {k}"
     return k
 
 

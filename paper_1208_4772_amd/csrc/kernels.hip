@@ -348,6 +348,69 @@ __global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
     sensor_body<T, P, CFL>(a, blockIdx.x);
 }
 
+// The sensor alone (no time-step bound) with one thread per element: the
+// block copies the densities of its kBlock elements into LDS (contiguous
+// runs of Np values, all loads issued before the first wait), then each
+// thread forms its element's modal energies and viscosity with the same
+// operations in the same order as sensor_body, so the results are the same
+// bits, without the two block-wide phases per element.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_sensor_elem(AvArgs<T> a) {
+    using O = Order<P>;
+    constexpr int Np = O::Np, Nfp = O::Nfp;
+    constexpr int NR = Np + 1;   // padded rows spread the threads over the LDS banks
+    __shared__ T sVi[Np * Np];
+    __shared__ T sR[kBlock * NR];
+    LdsCopy<T, Np * Np> vic;
+    vic.load(a.ops + (2 * Np * Np + Np * 3 * Nfp));
+    const long k0 = (long)blockIdx.x * kBlock;
+    const int nel = (int)min((long)kBlock, (long)a.K - k0);
+    const int nval = nel * Np;
+    T rv[Np];
+#pragma unroll
+    for (int r = 0; r < Np; ++r) {
+        const int z = min(int(threadIdx.x) + r * kBlock, nval - 1);
+        const int e = z / Np, j = z - e * Np;
+        rv[r] = a.U[(k0 + e) * kFields * Np + j];
+    }
+#pragma unroll
+    for (int r = 0; r < Np; ++r) {
+        const int z = int(threadIdx.x) + r * kBlock;
+        if (z < nval) {
+            const int e = z / Np, j = z - e * Np;
+            sR[e * NR + j] = rv[r];
+        }
+    }
+    vic.store(sVi);
+    __syncthreads();
+    if (int(threadIdx.x) >= nel) return;
+    const long k = k0 + threadIdx.x;
+    const T emax_k = a.emax[k];
+    T rho[Np];
+#pragma unroll
+    for (int j = 0; j < Np; ++j) rho[j] = sR[threadIdx.x * NR + j];
+    double num = 0, den = 0;
+#pragma unroll
+    for (int i = 0; i < Np; ++i) {
+        T uh = 0;
+#pragma unroll
+        for (int j = 0; j < Np; ++j) uh += sVi[i * Np + j] * rho[j];
+        const double e2 = double(uh) * double(uh);
+        den += e2;
+        if (i >= Np - Nfp) num += e2;
+    }
+    double emax = double(emax_k);
+    double e = 0.0;
+    if (den > 1e-300 && num > 0.0) {
+        double sk = log10(num / den);
+        if (sk > a.s0 + a.kappa)
+            e = emax;
+        else if (sk >= a.s0 - a.kappa)
+            e = 0.5 * emax * (1.0 + sin(M_PI * (sk - a.s0) / (2.0 * a.kappa)));
+    }
+    a.eps_out[k] = T(e);
+}
+
 // Auxiliary variable of the viscous system, q = sigma grad U (sigma =
 // sqrt eps_k), strong form with the central trace (sigma U)*:
 //   Q_x = sigma (r_x Dr U + s_x Ds U) + LIFT [Fscale n_x ((sigma U)* - sigma U-)]
@@ -957,7 +1020,8 @@ static hipError_t sensor_t(const DevMesh &m, const void *U, void *eps, unsigned 
         if (vmax)
             hipLaunchKernelGGL((k_sensor<T, P, true>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
         else
-            hipLaunchKernelGGL((k_sensor<T, P, false>), dim3(nblocks<P>(m.K)), dim3(kBlock), 0, st, a);
+            hipLaunchKernelGGL((k_sensor_elem<T, P>), dim3((m.K + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                               a);
         return hipGetLastError();
     });
 }

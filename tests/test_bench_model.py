@@ -33,4 +33,4 @@ def test_viscous_stage_counts_its_three_launches():
     # values each way) on top of the inviscid figure
     assert b_av - b_inv > case.K * 2 * 8 * case.Np * 4
     assert bench.stage_kernel_label(case, "fp32", 0) == \
-        "k_sensor<3> + k_avgrad<3> + k_stage_mfma<3,false,4,true>"
+        "k_sensor_elem<3> + k_avgrad<3> + k_stage_mfma<3,false,4,true>"
