@@ -820,6 +820,9 @@ struct Group {
     void *items = nullptr;
     size_t items_cap = 0;
     int nitems = 0;
+    void *eitems = nullptr;        // viscous: (job, block of 256 elements) for the per-element sensor
+    size_t eitems_cap = 0;
+    int neitems = 0;
 };
 
 }  // namespace
@@ -840,6 +843,7 @@ struct dg_batch {
             if (g.jobs) (void)hipFree(g.jobs);
             if (g.avjobs) (void)hipFree(g.avjobs);
             if (g.items) (void)hipFree(g.items);
+            if (g.eitems) (void)hipFree(g.eitems);
         }
     }
 };
@@ -880,12 +884,14 @@ int rebuild(dg_batch *b, hipStream_t st) {
                 g.avjobs_cap = o.avjobs_cap;
                 g.items = o.items;
                 g.items_cap = o.items_cap;
-                o.jobs = o.avjobs = o.items = nullptr;
+                g.eitems = o.eitems;
+                g.eitems_cap = o.eitems_cap;
+                o.jobs = o.avjobs = o.items = o.eitems = nullptr;
             }
         const size_t nj = g.slots.size();
         const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
         std::vector<char> jobs(2 * 5 * nj * rec), avjobs(g.av ? 2 * 5 * nj * arec : 0);
-        std::vector<int> items;
+        std::vector<int> items, eitems;
         for (size_t j = 0; j < nj; ++j) {
             Slot &s = b->slots[g.slots[j]];
             dg_mesh *m = s.mesh;
@@ -923,8 +929,16 @@ int rebuild(dg_batch *b, hipStream_t st) {
                 items.push_back(int(j));
                 items.push_back(tt);
             }
+            if (g.av) {
+                const int ne = sensor_elem_blocks(m->dm);
+                for (int tt = 0; tt < ne; ++tt) {
+                    eitems.push_back(int(j));
+                    eitems.push_back(tt);
+                }
+            }
         }
         g.nitems = int(items.size() / 2);
+        g.neitems = int(eitems.size() / 2);
         auto grow = [&](void **p, size_t *cap, size_t need) -> int {
             if (*cap >= need) return DG_OK;
             if (*p) (void)hipFree(*p);
@@ -940,6 +954,9 @@ int rebuild(dg_batch *b, hipStream_t st) {
         if (g.av) {
             if (int rc = grow(&g.avjobs, &g.avjobs_cap, avjobs.size())) return rc;
             HIP_TRY(hipMemcpyAsync(g.avjobs, avjobs.data(), avjobs.size(), hipMemcpyHostToDevice, st));
+            if (int rc = grow(&g.eitems, &g.eitems_cap, eitems.size() * sizeof(int))) return rc;
+            HIP_TRY(hipMemcpyAsync(g.eitems, eitems.data(), eitems.size() * sizeof(int), hipMemcpyHostToDevice,
+                                   st));
         }
         HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
     }
@@ -947,6 +964,7 @@ int rebuild(dg_batch *b, hipStream_t st) {
         if (o.jobs) (void)hipFree(o.jobs);
         if (o.avjobs) (void)hipFree(o.avjobs);
         if (o.items) (void)hipFree(o.items);
+        if (o.eitems) (void)hipFree(o.eitems);
     }
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
@@ -964,7 +982,7 @@ int batch_step(dg_batch *b, int ps, hipStream_t st) {
         for (const Group &g : b->groups) {
             if (g.av) {
                 const char *avjobs = static_cast<const char *>(g.avjobs) + (ps * 5 + s5) * g.slots.size() * arec;
-                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.nitems, st));
+                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.nitems, g.eitems, g.neitems, st));
             }
             const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * g.slots.size() * rec;
             HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, jobs, g.items, g.nitems, st));

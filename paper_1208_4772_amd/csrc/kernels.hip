@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_sensor(AvArgs<T> a) {
 // operations in the same order as sensor_body, so the results are the same
 // bits, without the two block-wide phases per element.
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_sensor_elem(AvArgs<T> a) {
+__device__ __forceinline__ void sensor_elem_body(const AvArgs<T> &a, const int tile) {
     using O = Order<P>;
     constexpr int Np = O::Np, Nfp = O::Nfp;
     constexpr int NR = Np + 1;   // padded rows spread the threads over the LDS banks
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_sensor_elem(AvArgs<T> a) {
     __shared__ T sR[kBlock * NR];
     LdsCopy<T, Np * Np> vic;
     vic.load(a.ops + (2 * Np * Np + Np * 3 * Nfp));
-    const long k0 = (long)blockIdx.x * kBlock;
+    const long k0 = (long)tile * kBlock;
     const int nel = (int)min((long)kBlock, (long)a.K - k0);
     const int nval = nel * Np;
     T rv[Np];
@@ -409,6 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_sensor_elem(AvArgs<T> a) {
             e = 0.5 * emax * (1.0 + sin(M_PI * (sk - a.s0) / (2.0 * a.kappa)));
     }
     a.eps_out[k] = T(e);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_sensor_elem(AvArgs<T> a) {
+    sensor_elem_body<T, P>(a, blockIdx.x);
 }
 
 // Auxiliary variable of the viscous system, q = sigma grad U (sigma =
@@ -509,6 +514,15 @@ __global__ __launch_bounds__(kBlock) void k_sensor_batch(const AvArgs<float> *__
     if ((int)blockIdx.x >= nitems) return;
     const int2 it = items[blockIdx.x];
     sensor_body<float, P, CFL>(jobs[it.x], it.y);
+}
+
+// Batched per-element sensor: work item = (job, block of kBlock elements).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_sensor_elem_batch(const AvArgs<float> *__restrict__ jobs,
+                                                              const int2 *__restrict__ items, int nitems) {
+    if ((int)blockIdx.x >= nitems) return;
+    const int2 it = items[blockIdx.x];
+    sensor_elem_body<float, P>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -1048,16 +1062,20 @@ void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned 
     std::memcpy(out, &a, sizeof(a));
 }
 
-hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems, hipStream_t st) {
+int sensor_elem_blocks(const DevMesh &m) { return (m.K + kBlock - 1) / kBlock; }
+
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems,
+                           const void *eitems, int neitems, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const auto *j = static_cast<const AvArgs<float> *>(jobs);
     const auto *it = static_cast<const int2 *>(items);
+    const auto *eit = static_cast<const int2 *>(eitems);
     return with_order(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
         if (cfl)
             hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
-        else
-            hipLaunchKernelGGL((k_sensor_batch<PP, false>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
+        else if (neitems > 0)
+            hipLaunchKernelGGL((k_sensor_elem_batch<PP>), dim3(neitems), dim3(kBlock), 0, st, j, eit, neitems);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);

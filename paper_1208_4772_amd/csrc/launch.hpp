@@ -136,7 +136,11 @@ hipError_t launch_avgrad(const DevMesh &m, const void *U, const void *eps, void 
 // gradient over all of them
 size_t av_args_bytes();
 void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned long long *vmax, void *out);
-hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems, hipStream_t st);
+// items: (job, tile) pairs of the stage kernel's tiles; eitems: (job, block)
+// pairs of blocks of 256 elements for the per-element sensor
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems,
+                           const void *eitems, int neitems, hipStream_t st);
+int sensor_elem_blocks(const DevMesh &m);
 // CFL reduction -> scal[S_DT] (dt_fixed > 0 overrides), accumulates S_T,
 // S_DTMIN/MAX, S_STEPS; raises *flag on bad states.
 hipError_t launch_cfl(const DevMesh &m, const void *U, const void *eps, double dt_fixed,
