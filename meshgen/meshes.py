@@ -181,6 +181,44 @@ def periodic_square(N: int, L: float = 10.0, jitter: float = 0.1,
     return mesh
 
 
+def channel(Nx: int, Ny: int, L: float = 10.0, H: float = 5.0, jitter: float = 0.1,
+            jitter_seed: int = 7, perm_seed: Optional[int] = None) -> Mesh:
+    """[0,L] x [0,H], periodic in x, slip walls at y=0 and y=H; 2*Nx*Ny
+    triangles (cells split along the (i,j)->(i+1,j+1) diagonal).  Vertices
+    off the seam and the walls move by U(-jitter*h, jitter*h) per coordinate
+    (h the smaller cell side)."""
+    if Nx < 3 or Ny < 2:
+        raise ValueError("Nx >= 3, Ny >= 2")
+    hx, hy = L / Nx, H / Ny
+    h = min(hx, hy)
+    nx1, ny1 = Nx + 1, Ny + 1
+    ii, jj = np.meshgrid(np.arange(nx1), np.arange(ny1), indexing="ij")
+    VX = (ii * hx).astype(np.float64).ravel()
+    VY = (jj * hy).astype(np.float64).ravel()
+    rng = np.random.default_rng(jitter_seed)
+    d = rng.uniform(-jitter * h, jitter * h, size=(2, nx1 * ny1))
+    interior = ((ii > 0) & (ii < Nx) & (jj > 0) & (jj < Ny)).ravel()
+    VX[interior] += d[0, interior]
+    VY[interior] += d[1, interior]
+
+    def vid(i, j):
+        return i * ny1 + j
+
+    ci, cj = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="ij")
+    ci = ci.ravel()
+    cj = cj.ravel()
+    EToV = np.empty((2 * Nx * Ny, 3), dtype=np.int64)
+    EToV[0::2] = np.stack([vid(ci, cj), vid(ci + 1, cj), vid(ci + 1, cj + 1)], axis=1)
+    EToV[1::2] = np.stack([vid(ci, cj), vid(ci + 1, cj + 1), vid(ci, cj + 1)], axis=1)
+    key = ((ii % Nx) * ny1 + jj).ravel()
+    EToE, EToF, bc = connect(EToV, key, lambda k, f: BC_WALL)
+    mesh = Mesh(VX, VY, EToV, EToE, EToF, bc, f"channel_{Nx}x{Ny}", None, None,
+                dict(Nx=Nx, Ny=Ny, L=L, H=H, h=h, periodic=(L, None)))
+    if perm_seed is not None:
+        mesh = permute_elements(mesh, np.random.default_rng(perm_seed).permutation(mesh.K))
+    return mesh
+
+
 def _orient_ccw(VX, VY, EToV):
     x = VX[EToV]
     y = VY[EToV]
@@ -192,10 +230,14 @@ def _orient_ccw(VX, VY, EToV):
 
 
 def _ogrid(Xs, Ys, Nt, Nr, jitter, seed, wall_curve_param, name, info,
-           inner_bc=BC_WALL):
+           inner_bc=BC_WALL, mirror_split=False):
     """O-grid triangles from vertex arrays Xs/Ys of shape (Nt, Nr+1).
 
-    Column j=0 is the wall, j=Nr the far field; index i is periodic.
+    Column j=0 is the wall, j=Nr the far field; index i is periodic.  Cells
+    are split along their (i,j)->(i+1,j+1) diagonal; with ``mirror_split``
+    the cells of the second half (i >= Nt/2) take the other diagonal, so that
+    an unjittered grid that is mirror-symmetric in i -> Nt-i gives a mirror-
+    symmetric triangulation.
     """
     VX = Xs.ravel().copy()
     VY = Ys.ravel().copy()
@@ -224,6 +266,10 @@ def _ogrid(Xs, Ys, Nt, Nr, jitter, seed, wall_curve_param, name, info,
     cj = cj.ravel()
     t1 = np.stack([vid(ci, cj), vid(ci + 1, cj), vid(ci + 1, cj + 1)], axis=1)
     t2 = np.stack([vid(ci, cj), vid(ci + 1, cj + 1), vid(ci, cj + 1)], axis=1)
+    if mirror_split:
+        second = ci >= Nt // 2
+        t1[second] = np.stack([vid(ci, cj), vid(ci + 1, cj), vid(ci, cj + 1)], axis=1)[second]
+        t2[second] = np.stack([vid(ci + 1, cj), vid(ci + 1, cj + 1), vid(ci, cj + 1)], axis=1)[second]
     EToV = np.empty((2 * Nt * Nr, 3), dtype=np.int64)
     EToV[0::2] = t1
     EToV[1::2] = t2
@@ -262,14 +308,16 @@ def _ogrid(Xs, Ys, Nt, Nr, jitter, seed, wall_curve_param, name, info,
 
 def cylinder_annulus(Ntheta: int = 200, Nr: int = 50, R1: float = 1.0,
                      R2: float = 20.0, jitter: float = 0.1, seed: int = 38,
-                     curved: bool = True, inner_bc: int = BC_WALL) -> Mesh:
+                     curved: bool = True, inner_bc: int = BC_WALL,
+                     mirror_split: bool = False) -> Mesh:
     """Annulus R1<=r<=R2 around the origin, 2*Ntheta*Nr triangles.
 
     Radii are geometric, r_j = R1*(R2/R1)^(j/Nr).  Interior vertices get a
     seeded jitter of ``jitter`` times the local spacing.  The inner circle is a
     slip wall (curved onto the exact circle when ``curved``), the outer circle
     the far field.  ``inner_bc=BC_FARFIELD`` gives a far-field-only annulus
-    (straight inner boundary).
+    (straight inner boundary).  ``mirror_split`` (with ``jitter=0`` and even
+    ``Ntheta``) makes the triangulation mirror-symmetric about the x axis.
     """
     th = 2 * np.pi * np.arange(Ntheta) / Ntheta
     r = R1 * (R2 / R1) ** (np.arange(Nr + 1) / Nr)
@@ -286,7 +334,8 @@ def cylinder_annulus(Ntheta: int = 200, Nr: int = 50, R1: float = 1.0,
         curve = (param_of_vertex, point_of_param)
     return _ogrid(Xs, Ys, Ntheta, Nr, jitter, seed, curve,
                   f"cylinder_{Ntheta}x{Nr}",
-                  dict(R1=R1, R2=R2, chord=2 * R1, wall="circle"), inner_bc)
+                  dict(R1=R1, R2=R2, chord=2 * R1, wall="circle"), inner_bc,
+                  mirror_split)
 
 
 def naca4_thickness(x, t=0.12):
@@ -311,7 +360,7 @@ def naca_point(beta, t=0.12):
 
 def naca4_ogrid(Ntheta: int = 600, Nr: int = 100, t: float = 0.12,
                 R: float = 30.0, growth: float = 1.06, jitter: float = 0.02,
-                seed: int = 80, curved: bool = True) -> Mesh:
+                seed: int = 80, curved: bool = True, mirror_split: bool = False) -> Mesh:
     """O-grid around a symmetric 4-digit airfoil (chord 1) inside a circular
     far field of radius R centred at (0.5, 0); 2*Ntheta*Nr triangles.
 
@@ -337,7 +386,7 @@ def naca4_ogrid(Ntheta: int = 600, Nr: int = 100, t: float = 0.12,
         curve = (param_of_vertex, point_of_param)
     return _ogrid(X, Y, Ntheta, Nr, jitter, seed, curve,
                   f"naca00{int(round(t * 100)):02d}_{Ntheta}x{Nr}",
-                  dict(R=R, chord=1.0, wall="naca", thickness=t))
+                  dict(R=R, chord=1.0, wall="naca", thickness=t), BC_WALL, mirror_split)
 
 
 # ---------------------------------------------------------------------------

@@ -341,11 +341,49 @@ void oracle_av_gradient(const oracle_mesh *m, const double *U, const double *eps
 /* right-hand side                                                        */
 /* ---------------------------------------------------------------------- */
 
+/* Normal viscous flux at a face node: visc_m = sigma- Q-.n (the element's
+ * own trace) and the numerical flux visc_star = (sigma Q)*.n.
+ * Interior: the central value 1/2 (sigma- Q- + sigma+ Q+).n.
+ * Slip wall: the mean with the ghost gradient that the mirror ghost state
+ * implies.  Mirroring a field across the wall flips the sign of its normal
+ * derivative; rho and E are mirrored unchanged, so their (sigma Q)*.n is 0,
+ * and the momentum m is mirrored to m - 2 (m.n) n, so of its normal
+ * derivative g = (Q_x n_x + Q_y n_y) only the component along n survives:
+ * (sigma Q)*.n = sigma- (g.n) n.
+ * Far field: the element's own value sigma- Q-.n. */
+static void viscous_face_flux(const oracle_mesh *m, long k, int f, int v, long kn, int vn,
+                              double nx, double ny, double visc_m[NF], double visc_star[NF]) {
+    const int Np = m->Np;
+    const double *Q = m->Q, *eps = m->eps;
+    double sig = sqrt(eps[k]);
+    double g[NF];
+    for (int c = 0; c < NF; ++c) {
+        g[c] = nx * Q[((k * 2 + 0) * NF + c) * Np + v] + ny * Q[((k * 2 + 1) * NF + c) * Np + v];
+        visc_m[c] = sig * g[c];
+    }
+    int code = m->bc[k * 3 + f];
+    if (code == BC_INTERIOR) {
+        double sigp = sqrt(eps[kn]);
+        for (int c = 0; c < NF; ++c) {
+            double gp = nx * Q[((kn * 2 + 0) * NF + c) * Np + vn] +
+                        ny * Q[((kn * 2 + 1) * NF + c) * Np + vn];
+            visc_star[c] = 0.5 * (visc_m[c] + sigp * gp);
+        }
+    } else if (code == BC_WALL) {
+        double gn = g[1] * nx + g[2] * ny;
+        visc_star[0] = 0.0;
+        visc_star[1] = sig * gn * nx;
+        visc_star[2] = sig * gn * ny;
+        visc_star[3] = 0.0;
+    } else {
+        for (int c = 0; c < NF; ++c) visc_star[c] = visc_m[c];
+    }
+}
+
 /* dU/dt = -(r_x Dr F + s_x Ds F + r_y Dr G + s_y Ds G)
  *         + LIFT [Fscale (n.F(U-) - F*)]
  * where, with artificial viscosity, F and G include -sigma Q_x, -sigma Q_y
- * and F* includes -(sigma Q)*.n, (sigma Q)* = 1/2 (sigma- Q- + sigma+ Q+)
- * (boundary: sigma- Q-). */
+ * and F* includes -(sigma Q)*.n (viscous_face_flux). */
 void oracle_rhs(oracle_mesh *m, const double *U, double *rhs) {
     const int Np = m->Np, Nfp = m->Nfp, Nf3 = 3 * m->Nfp;
     const double g = m->gamma;
@@ -394,22 +432,12 @@ void oracle_rhs(oracle_mesh *m, const double *U, double *rhs) {
                     oracle_lf_flux(g, um, up, nx, ny, fstar);
                 }
                 int v = m->Fmask[f * Nfp + j];
+                double visc_m[NF] = {0}, visc_star[NF] = {0};
+                if (av) viscous_face_flux(m, k, f, v, kn, vn, nx, ny, visc_m, visc_star);
                 for (int c = 0; c < NF; ++c) {
+                    /* n.(F - sigma Q)(U-) - (F* - (sigma Q)*.n) */
                     double d = fm[c] - fstar[c];
-                    if (av) {
-                        double qxm = Q[((k * 2 + 0) * NF + c) * Np + v];
-                        double qym = Q[((k * 2 + 1) * NF + c) * Np + v];
-                        double visc_m = sig * (nx * qxm + ny * qym);
-                        double visc_star = visc_m;
-                        if (kn >= 0) {
-                            double sigp = sqrt(eps[kn]);
-                            double qxp = Q[((kn * 2 + 0) * NF + c) * Np + vn];
-                            double qyp = Q[((kn * 2 + 1) * NF + c) * Np + vn];
-                            visc_star = 0.5 * (visc_m + sigp * (nx * qxp + ny * qyp));
-                        }
-                        /* n.(F - sigma Q)(U-) - (F* - (sigma Q)*.n) */
-                        d += -visc_m + visc_star;
-                    }
+                    if (av) d += -visc_m[c] + visc_star[c];
                     dfl[f * Nfp + j][c] = m->Fscale[q] * d;
                 }
             }

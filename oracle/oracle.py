@@ -23,15 +23,26 @@ LIB = os.path.join(HERE, "liboracle.so")
 NF = 4
 
 
-def build(force: bool = True) -> str:
-    """Compile ``dg_oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + f".tmp{os.getpid()}"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+# Second build of the same source whose floating-point expressions are
+# contracted into fused multiply-adds wherever the compiler can: the same
+# arithmetic in a different rounding order, used to measure how far two valid
+# evaluation orders of the oracle differ on ill-conditioned meshes.
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
+FMA_FLAGS = ["-mfma", "-ffp-contract=fast"]
+
+
+def build(force: bool = True, fma: bool = False) -> str:
+    """Compile ``dg_oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP, no
+    contraction); ``fma``: the contracted build ``liboracle_fma.so``."""
+    out = LIB_FMA if fma else LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + f".tmp{os.getpid()}"
+    flags = FMA_FLAGS if fma else ["-ffp-contract=off"]
+    subprocess.check_call(["gcc", "-O2", *flags, "-fopenmp", "-fPIC", "-shared", "-Wall",
                            "-o", tmp, SRC, "-lm"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 class _Mesh(C.Structure):
@@ -54,13 +65,13 @@ class _Mesh(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = build(force=False)
+def lib(fma: bool = False):
+    """The oracle's C core (``fma``: the contracted build)."""
+    if fma not in _libs:
+        path = build(force=False, fma=fma)
         L = C.CDLL(path)
         vp, d, i, l = C.c_void_p, C.c_double, C.c_int, C.c_long
         L.oracle_geometry.restype = l
@@ -79,8 +90,8 @@ def lib():
         L.oracle_rk_coefficients.argtypes = [vp, vp]
         L.oracle_set_threads.argtypes = [i]
         L.oracle_max_threads.restype = i
-        _lib = L
-    return _lib
+        _libs[fma] = L
+    return _libs[fma]
 
 
 def _p(a):
@@ -123,12 +134,14 @@ class Oracle:
 
     ``x``, ``y`` are the (K, Np) node coordinates in this module's node order
     (:func:`oracle.refelem.nodes`).  States are (K, 4, Np) float64 arrays.
+    ``fma``: evaluate with the contracted build of the same source.
     """
 
     def __init__(self, mesh, P, x, y, freestream=(1.0, 0.0, 0.0, 2.5), gamma=1.4,
                  cfl=0.5, av=False, av_eps0=0.3, av_s0=None, av_kappa=1.0,
-                 no_euler_flux=False, eps_override=-1.0):
+                 no_euler_flux=False, eps_override=-1.0, fma=False):
         R = ref(P)
+        self._L = lib(fma)
         self.ref = R
         self.P, self.Np, self.Nfp = P, R.Np, R.Nfp
         self.K = int(mesh.K)
@@ -179,7 +192,7 @@ class Oracle:
         m.eps_override = eps_override
         m.eps, m.Q = _p(self.eps).value, _p(self.Q).value
         self.m = m
-        self.bad_jacobians = lib().oracle_geometry(
+        self.bad_jacobians = self._L.oracle_geometry(
             C.byref(m), _p(x), _p(y), *(_p(self.geo[n]) for n in
                                          ("rx", "sx", "ry", "sy", "J", "nx", "ny", "sJ", "Fscale")))
 
@@ -200,39 +213,39 @@ class Oracle:
     def rhs(self, U):
         U = self._state(U)
         out = np.empty_like(U)
-        lib().oracle_rhs(C.byref(self.m), _p(U), _p(out))
+        self._L.oracle_rhs(C.byref(self.m), _p(U), _p(out))
         return out
 
     def sensor(self, U):
         U = self._state(U)
         eps = np.empty(self.K)
-        lib().oracle_sensor(C.byref(self.m), _p(U), _p(eps))
+        self._L.oracle_sensor(C.byref(self.m), _p(U), _p(eps))
         return eps
 
     def av_gradient(self, U, eps):
         U = self._state(U)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         Q = np.empty((self.K, 2, NF, self.Np))
-        lib().oracle_av_gradient(C.byref(self.m), _p(U), _p(eps), _p(Q))
+        self._L.oracle_av_gradient(C.byref(self.m), _p(U), _p(eps), _p(Q))
         return Q
 
     def dt(self, U):
         U = self._state(U)
         flag = C.c_int(0)
-        d = lib().oracle_dt(C.byref(self.m), _p(U), C.byref(flag))
+        d = self._L.oracle_dt(C.byref(self.m), _p(U), C.byref(flag))
         return d, flag.value
 
     def totals(self, U):
         U = self._state(U)
         out = np.zeros(4)
-        lib().oracle_totals(C.byref(self.m), _p(U), _p(out))
+        self._L.oracle_totals(C.byref(self.m), _p(U), _p(out))
         return out
 
     def residual(self, U):
         U = self._state(U)
         scratch = np.empty_like(U)
         out = np.zeros(4)
-        lib().oracle_residual(C.byref(self.m), _p(U), _p(scratch), _p(out))
+        self._L.oracle_residual(C.byref(self.m), _p(U), _p(scratch), _p(out))
         return out
 
     def run(self, U, nsteps, dt=0.0):
@@ -242,6 +255,6 @@ class Oracle:
         scratch = np.zeros_like(U)
         mm = np.zeros(2)
         flag = C.c_int(0)
-        t = lib().oracle_run(C.byref(self.m), _p(U), int(nsteps), float(dt), _p(R),
+        t = self._L.oracle_run(C.byref(self.m), _p(U), int(nsteps), float(dt), _p(R),
                              _p(scratch), _p(mm), C.byref(flag))
         return U, dict(t=t, dt_min=mm[0], dt_max=mm[1], flag=flag.value)

@@ -101,10 +101,11 @@ def _warp(N: int, rout: np.ndarray) -> np.ndarray:
     return out
 
 
-def nodes(P: int):
+def nodes(P: int, alpha: float | None = None):
     """Warp-and-blend nodes (r, s) on T, ordered in rows of constant s
-    (increasing s), increasing r within a row."""
-    alpha = ALPHA_OPT[P]
+    (increasing s), increasing r within a row.  ``alpha``: the blending
+    exponent (default: the table's value for this order)."""
+    alpha = ALPHA_OPT[P] if alpha is None else float(alpha)
     L1, L3 = [], []
     for n in range(P + 1):          # row index: L1 = n/P  (s = 2 L1 - 1)
         for m in range(P + 1 - n):  # position in the row: L3 = m/P
