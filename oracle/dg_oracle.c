@@ -38,6 +38,19 @@
 
 enum { BC_INTERIOR = 0, BC_WALL = 1, BC_FARFIELD = 2 };
 
+/* Cubature operators of the over-integrated weak form (Section 2, eqs.
+ * stiffness, mass, face_mass, semidiscrete): a rule of ncub points on the
+ * reference triangle and ng Gauss points per face. */
+typedef struct {
+    int ncub, ng;
+    const double *wq;        /* [ncub] cubature weights (sum 2) */
+    const double *Icub;      /* [ncub][Np] nodal basis at the cubature points */
+    const double *Drc, *Dsc; /* [ncub][Np] its r and s derivatives there */
+    const double *wg;        /* [ng] Gauss weights on [-1, 1] */
+    const double *If;        /* [ng][Nfp] face-node Lagrange basis at the Gauss points */
+    const double *Drg, *Dsg; /* [3][ng][Np] basis derivatives at each face's Gauss points */
+} oracle_weak;
+
 typedef struct {
     int K, P, Np, Nfp;
     double gamma;
@@ -58,11 +71,16 @@ typedef struct {
     double cfl;
     int av_enable;
     double av_eps0, av_s0, av_kappa;
+    int riemann;          /* numerical flux: 0 local Lax-Friedrichs, 1 HLLC */
     /* test switches */
     int no_euler_flux;    /* 1: drop the inviscid flux (pure diffusion tests) */
     double eps_override;  /* >= 0: this viscosity in every element */
     /* scratch owned by the caller: [K] eps, [K][2][NF][Np] Q */
     double *eps, *Q;
+    /* over-integrated weak form (NULL: the nodal strong form) with the
+     * element node coordinates it needs for its metric terms */
+    const oracle_weak *weak;
+    const double *x, *y;     /* [K][Np] */
 } oracle_mesh;
 
 /* ---------------------------------------------------------------------- */
@@ -108,6 +126,59 @@ void oracle_lf_flux(double g, const double um[NF], const double up[NF],
     double lam = lm > lp ? lm : lp;
     for (int c = 0; c < NF; ++c)
         fstar[c] = 0.5 * (fm[c] + fp[c]) - 0.5 * lam * (up[c] - um[c]);
+}
+
+/* HLLC flux (Toro, Spruce and Speares; Toro's book, chapter 10) in the
+ * frame of the face normal n, a selectable alternative to the local
+ * Lax-Friedrichs flux (the paper reports both, Section 2 after eq. weak_dg).
+ * Wave speeds: S_L = min(v_n- - c-, v_n+ - c+), S_R = max(v_n- + c-,
+ * v_n+ + c+) (Davis); contact speed
+ *   S* = (p+ - p- + rho- v_n- (S_L - v_n-) - rho+ v_n+ (S_R - v_n+))
+ *        / (rho- (S_L - v_n-) - rho+ (S_R - v_n+)).
+ * Star state of side K (velocity v_K + (S* - v_nK) n, i.e. the normal
+ * velocity replaced by S*):
+ *   U*_K = rho_K (S_K - v_nK)/(S_K - S*) (1, v_K + (S* - v_nK) n,
+ *          E_K/rho_K + (S* - v_nK)(S* + p_K/(rho_K (S_K - v_nK)))).
+ * F* = n.F(U-) if S_L >= 0; n.F(U-) + S_L (U*_L - U-) if S_L < 0 <= S*;
+ * n.F(U+) + S_R (U*_R - U+) if S* < 0 < S_R; n.F(U+) if S_R <= 0. */
+static void hllc_star(double g, const double u[NF], double nx, double ny, double SK, double Ss,
+                      double out[NF]) {
+    double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+    double p = pressure(g, u);
+    double vn = vx * nx + vy * ny;
+    double f = rho * (SK - vn) / (SK - Ss);
+    out[0] = f;
+    out[1] = f * (vx + (Ss - vn) * nx);
+    out[2] = f * (vy + (Ss - vn) * ny);
+    out[3] = f * (u[3] / rho + (Ss - vn) * (Ss + p / (rho * (SK - vn))));
+}
+
+void oracle_hllc_flux(double g, const double um[NF], const double up[NF],
+                      double nx, double ny, double fstar[NF]) {
+    double fm[NF], fp[NF], lm, lp;
+    normal_flux(g, um, nx, ny, fm, &lm);
+    normal_flux(g, up, nx, ny, fp, &lp);
+    double rl = um[0], rr = up[0];
+    double vnl = (um[1] * nx + um[2] * ny) / rl, vnr = (up[1] * nx + up[2] * ny) / rr;
+    double pl = pressure(g, um), pr = pressure(g, up);
+    double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+    double SL = fmin(vnl - cl, vnr - cr);
+    double SR = fmax(vnl + cl, vnr + cr);
+    double Ss = (pr - pl + rl * vnl * (SL - vnl) - rr * vnr * (SR - vnr)) /
+                (rl * (SL - vnl) - rr * (SR - vnr));
+    if (SL >= 0.0) {
+        for (int c = 0; c < NF; ++c) fstar[c] = fm[c];
+    } else if (Ss >= 0.0) {
+        double us[NF];
+        hllc_star(g, um, nx, ny, SL, Ss, us);
+        for (int c = 0; c < NF; ++c) fstar[c] = fm[c] + SL * (us[c] - um[c]);
+    } else if (SR > 0.0) {
+        double us[NF];
+        hllc_star(g, up, nx, ny, SR, Ss, us);
+        for (int c = 0; c < NF; ++c) fstar[c] = fp[c] + SR * (us[c] - up[c]);
+    } else {
+        for (int c = 0; c < NF; ++c) fstar[c] = fp[c];
+    }
 }
 
 /* Ghost state of a boundary face node (outward unit normal n).
@@ -380,11 +451,137 @@ static void viscous_face_flux(const oracle_mesh *m, long k, int f, int v, long k
     }
 }
 
+/* Right-hand side in the over-integrated weak form.  Per element k, with
+ * phi_i the nodal basis and u = sum_j phi_j u_j:
+ *   M_k dU/dt = V - S,
+ *   V_i = int_k grad phi_i . (F(u), G(u)) dx
+ *       = sum_q w_q J_q [dphi_i/dr (r_x F + r_y G) + dphi_i/ds (s_x F + s_y G)](x_q),
+ *   S_i = oint_dk phi_i F*.n ds = sum_f sum_g w_g sJ_fg phi_i(x_fg) F*(u-, u+)_fg,
+ *   M_k,ij = sum_q w_q J_q phi_i(x_q) phi_j(x_q),
+ * with the metric terms, J, normals and sJ of the isoparametric map at each
+ * cubature and face Gauss point, u- the element's face polynomial and u+
+ * the neighbour's (or the boundary ghost state) at the same point; M_k is
+ * solved by Cholesky factorisation.  Inviscid: the artificial viscosity is
+ * defined for the nodal form only. */
+static void cholesky_solve(int n, double *A, double *b) {
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        d = sqrt(d);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / d;
+        }
+    }
+    for (int i = 0; i < n; ++i) {       /* L y = b */
+        double v = b[i];
+        for (int k = 0; k < i; ++k) v -= A[i * n + k] * b[k];
+        b[i] = v / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  /* L^T x = y */
+        double v = b[i];
+        for (int k = i + 1; k < n; ++k) v -= A[k * n + i] * b[k];
+        b[i] = v / A[i * n + i];
+    }
+}
+
+void oracle_rhs_weak(const oracle_mesh *m, const double *U, double *rhs) {
+    const oracle_weak *w = m->weak;
+    const int Np = m->Np, Nfp = m->Nfp, nq = w->ncub, ng = w->ng;
+    const double g = m->gamma;
+#pragma omp parallel for
+    for (long k = 0; k < m->K; ++k) {
+        const double *xk = m->x + k * Np, *yk = m->y + k * Np;
+        double V[NF][64] = {{0}}, S[NF][64] = {{0}}, M[64 * 64];
+        for (int i = 0; i < Np * Np; ++i) M[i] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double *ph = w->Icub + q * Np, *pr = w->Drc + q * Np, *ps = w->Dsc + q * Np;
+            double xr = 0, xs = 0, yr = 0, ys = 0, u[NF] = {0};
+            for (int j = 0; j < Np; ++j) {
+                xr += pr[j] * xk[j];
+                xs += ps[j] * xk[j];
+                yr += pr[j] * yk[j];
+                ys += ps[j] * yk[j];
+                for (int c = 0; c < NF; ++c) u[c] += ph[j] * U[(k * NF + c) * Np + j];
+            }
+            double J = xr * ys - xs * yr;
+            double rx = ys / J, sx = -yr / J, ry = -xs / J, sy = xr / J;
+            double F[NF], G[NF];
+            euler_flux(g, u, F, G);
+            double wJ = w->wq[q] * J;
+            for (int c = 0; c < NF; ++c) {
+                double a = wJ * (rx * F[c] + ry * G[c]);
+                double b = wJ * (sx * F[c] + sy * G[c]);
+                for (int i = 0; i < Np; ++i) V[c][i] += pr[i] * a + ps[i] * b;
+            }
+            for (int i = 0; i < Np; ++i)
+                for (int j = 0; j < Np; ++j) M[i * Np + j] += wJ * ph[i] * ph[j];
+        }
+        for (int f = 0; f < 3; ++f) {
+            int code = m->bc[k * 3 + f];
+            long kn = m->EToE[k * 3 + f];
+            int fn = m->EToF[k * 3 + f];
+            for (int gq = 0; gq < ng; ++gq) {
+                const double *lf = w->If + gq * Nfp;
+                const double *pr = w->Drg + (f * ng + gq) * Np, *ps = w->Dsg + (f * ng + gq) * Np;
+                double xr = 0, xs = 0, yr = 0, ys = 0;
+                for (int j = 0; j < Np; ++j) {
+                    xr += pr[j] * xk[j];
+                    xs += ps[j] * xk[j];
+                    yr += pr[j] * yk[j];
+                    ys += ps[j] * yk[j];
+                }
+                double ax, ay;
+                if (f == 0) { ax = yr; ay = -xr; }
+                else if (f == 1) { ax = ys - yr; ay = xr - xs; }
+                else { ax = -ys; ay = xs; }
+                double sJ = sqrt(ax * ax + ay * ay), nx = ax / sJ, ny = ay / sJ;
+                double um[NF] = {0}, up[NF] = {0}, fs[NF];
+                for (int j = 0; j < Nfp; ++j) {
+                    int v = m->Fmask[f * Nfp + j];
+                    for (int c = 0; c < NF; ++c) um[c] += lf[j] * U[(k * NF + c) * Np + v];
+                }
+                if (code == BC_INTERIOR) {
+                    /* the neighbour's face node Nfp-1-j sits on this face's node j */
+                    for (int j = 0; j < Nfp; ++j) {
+                        int v = m->Fmask[fn * Nfp + (Nfp - 1 - j)];
+                        for (int c = 0; c < NF; ++c) up[c] += lf[j] * U[(kn * NF + c) * Np + v];
+                    }
+                } else {
+                    oracle_ghost(g, code, um, nx, ny, m->freestream, up);
+                }
+                if (m->riemann == 1)
+                    oracle_hllc_flux(g, um, up, nx, ny, fs);
+                else
+                    oracle_lf_flux(g, um, up, nx, ny, fs);
+                double ws = w->wg[gq] * sJ;
+                for (int j = 0; j < Nfp; ++j) {
+                    int v = m->Fmask[f * Nfp + j];
+                    for (int c = 0; c < NF; ++c) S[c][v] += ws * lf[j] * fs[c];
+                }
+            }
+        }
+        for (int c = 0; c < NF; ++c) {
+            double A[64 * 64], b[64];
+            for (int i = 0; i < Np * Np; ++i) A[i] = M[i];
+            for (int i = 0; i < Np; ++i) b[i] = V[c][i] - S[c][i];
+            cholesky_solve(Np, A, b);
+            for (int i = 0; i < Np; ++i) rhs[(k * NF + c) * Np + i] = b[i];
+        }
+    }
+}
+
 /* dU/dt = -(r_x Dr F + s_x Ds F + r_y Dr G + s_y Ds G)
  *         + LIFT [Fscale (n.F(U-) - F*)]
  * where, with artificial viscosity, F and G include -sigma Q_x, -sigma Q_y
  * and F* includes -(sigma Q)*.n (viscous_face_flux). */
 void oracle_rhs(oracle_mesh *m, const double *U, double *rhs) {
+    if (m->weak) {
+        oracle_rhs_weak(m, U, rhs);
+        return;
+    }
     const int Np = m->Np, Nfp = m->Nfp, Nf3 = 3 * m->Nfp;
     const double g = m->gamma;
     int av = m->av_enable || m->eps_override >= 0.0;
@@ -429,7 +626,10 @@ void oracle_rhs(oracle_mesh *m, const double *U, double *rhs) {
                     for (int c = 0; c < NF; ++c) fm[c] = fstar[c] = 0.0;
                 } else {
                     normal_flux(g, um, nx, ny, fm, &lam);
-                    oracle_lf_flux(g, um, up, nx, ny, fstar);
+                    if (m->riemann == 1)
+                        oracle_hllc_flux(g, um, up, nx, ny, fstar);
+                    else
+                        oracle_lf_flux(g, um, up, nx, ny, fstar);
                 }
                 int v = m->Fmask[f * Nfp + j];
                 double visc_m[NF] = {0}, visc_star[NF] = {0};

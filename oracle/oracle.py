@@ -45,6 +45,12 @@ def build(force: bool = True, fma: bool = False) -> str:
     return out
 
 
+class _Weak(C.Structure):
+    _fields_ = [("ncub", C.c_int), ("ng", C.c_int),
+                ("wq", C.c_void_p), ("Icub", C.c_void_p), ("Drc", C.c_void_p), ("Dsc", C.c_void_p),
+                ("wg", C.c_void_p), ("If", C.c_void_p), ("Drg", C.c_void_p), ("Dsg", C.c_void_p)]
+
+
 class _Mesh(C.Structure):
     _fields_ = [
         ("K", C.c_int), ("P", C.c_int), ("Np", C.c_int), ("Nfp", C.c_int),
@@ -59,9 +65,11 @@ class _Mesh(C.Structure):
         ("cfl", C.c_double),
         ("av_enable", C.c_int),
         ("av_eps0", C.c_double), ("av_s0", C.c_double), ("av_kappa", C.c_double),
+        ("riemann", C.c_int),
         ("no_euler_flux", C.c_int),
         ("eps_override", C.c_double),
         ("eps", C.c_void_p), ("Q", C.c_void_p),
+        ("weak", C.c_void_p), ("x", C.c_void_p), ("y", C.c_void_p),
     ]
 
 
@@ -86,6 +94,7 @@ def lib(fma: bool = False):
         L.oracle_run.argtypes = [vp, vp, i, d, vp, vp, vp, vp]
         L.oracle_residual.argtypes = [vp, vp, vp, vp]
         L.oracle_lf_flux.argtypes = [d, vp, vp, d, d, vp]
+        L.oracle_hllc_flux.argtypes = [d, vp, vp, d, d, vp]
         L.oracle_ghost.argtypes = [d, i, vp, d, d, vp, vp]
         L.oracle_rk_coefficients.argtypes = [vp, vp]
         L.oracle_set_threads.argtypes = [i]
@@ -121,6 +130,14 @@ def lf_flux(um, up, nx, ny, gamma=1.4):
     return out
 
 
+def hllc_flux(um, up, nx, ny, gamma=1.4):
+    um = np.ascontiguousarray(um, dtype=np.float64)
+    up = np.ascontiguousarray(up, dtype=np.float64)
+    out = np.zeros(4)
+    lib().oracle_hllc_flux(gamma, _p(um), _p(up), float(nx), float(ny), _p(out))
+    return out
+
+
 def ghost(code, um, nx, ny, qinf, gamma=1.4):
     um = np.ascontiguousarray(um, dtype=np.float64)
     qinf = np.ascontiguousarray(qinf, dtype=np.float64)
@@ -129,17 +146,27 @@ def ghost(code, um, nx, ny, qinf, gamma=1.4):
     return out
 
 
+def prolong(U, P, Q):
+    """State (K, 4, Np(P)) prolonged to order Q (p-refinement)."""
+    from .refelem import prolongation
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return np.ascontiguousarray(U @ prolongation(P, Q).T)
+
+
 class Oracle:
     """FP64 oracle bound to one mesh and order.
 
     ``x``, ``y`` are the (K, Np) node coordinates in this module's node order
     (:func:`oracle.refelem.nodes`).  States are (K, 4, Np) float64 arrays.
     ``fma``: evaluate with the contracted build of the same source.
+    ``riemann``: the numerical flux, "lf" (local Lax-Friedrichs) or "hllc".
+    ``weak``: the paper's over-integrated weak form (cubature and face Gauss
+    rules, per-element mass matrices) instead of the nodal strong form.
     """
 
     def __init__(self, mesh, P, x, y, freestream=(1.0, 0.0, 0.0, 2.5), gamma=1.4,
                  cfl=0.5, av=False, av_eps0=0.3, av_s0=None, av_kappa=1.0,
-                 no_euler_flux=False, eps_override=-1.0, fma=False):
+                 no_euler_flux=False, eps_override=-1.0, fma=False, riemann="lf", weak=False):
         R = ref(P)
         self._L = lib(fma)
         self.ref = R
@@ -188,9 +215,25 @@ class Oracle:
         m.av_eps0 = av_eps0
         m.av_s0 = -4.0 * math.log10(P) if av_s0 is None or (isinstance(av_s0, float) and math.isnan(av_s0)) else av_s0
         m.av_kappa = av_kappa
+        if riemann not in ("lf", "hllc"):
+            raise ValueError("riemann must be 'lf' or 'hllc'")
+        m.riemann = 1 if riemann == "hllc" else 0
         m.no_euler_flux = 1 if no_euler_flux else 0
         m.eps_override = eps_override
         m.eps, m.Q = _p(self.eps).value, _p(self.Q).value
+        self.weak = bool(weak)
+        if weak:
+            if av or eps_override >= 0.0 or no_euler_flux:
+                raise ValueError("the weak form is inviscid")
+            from .refelem import weak_ops
+            W = weak_ops(P)
+            wk = _Weak()
+            wk.ncub, wk.ng = W.ncub, W.ng
+            for name in ("wq", "Icub", "Drc", "Dsc", "wg", "If", "Drg", "Dsg"):
+                setattr(wk, name, _p(keep(getattr(W, name), np.float64)).value)
+            self._weak = wk
+            m.weak = C.addressof(wk)
+            m.x, m.y = _p(x).value, _p(y).value
         self.m = m
         self.bad_jacobians = self._L.oracle_geometry(
             C.byref(m), _p(x), _p(y), *(_p(self.geo[n]) for n in

@@ -245,3 +245,76 @@ class RefElem:
 @functools.lru_cache(maxsize=None)
 def ref(P: int) -> RefElem:
     return RefElem(P)
+
+
+def prolongation(P: int, Q: int) -> np.ndarray:
+    """(Np(Q), Np(P)) matrix evaluating a degree-P nodal polynomial at the
+    order-Q nodes (p-refinement, Section 5: the modal coefficients padded with
+    zeros).  The modes are ordered by total degree, so the first Np(P) modes
+    of order Q are exactly those of degree <= P."""
+    if Q < P:
+        raise ValueError("Q >= P")
+    return ref(Q).V[:, :n_nodes(P)] @ ref(P).Vinv
+
+
+# ---------------------------------------------------------------------------
+# cubature: the paper's over-integrated weak form
+# ---------------------------------------------------------------------------
+
+def cubature_points_per_direction(P: int) -> int:
+    """n for the rules below: exact for total degree 2n - 1 >= 3P."""
+    return (3 * P + 2) // 2
+
+
+def triangle_cubature(n: int):
+    """Collapsed (conical) product rule on T with n x n points (Stroud): n
+    Gauss-Legendre points in a and n Gauss-Jacobi points of weight (1 - b)
+    in b (the Jacobian of the collapse), mapped by r = (1+a)(1-b)/2 - 1,
+    s = b; weights w_a w_b / 2.  Exact for polynomials of total degree
+    <= 2n - 1 on T (area 2)."""
+    a, wa = special.roots_legendre(n)
+    b, wb = special.roots_jacobi(n, 1.0, 0.0)
+    A, B = np.meshgrid(a, b, indexing="ij")
+    WA, WB = np.meshgrid(wa, wb, indexing="ij")
+    r = 0.5 * (1.0 + A) * (1.0 - B) - 1.0
+    return r.ravel(), B.ravel(), (0.5 * WA * WB).ravel()
+
+
+class WeakOperators:
+    """Operators of the over-integrated weak form of order P: the nodal basis
+    and its derivatives at the cubature points (Icub, Drc, Dsc), the Gauss
+    rule of each face (wg at points tg of the face parameter, the same
+    counter-clockwise parameter as the face nodes), the face nodes' 1D
+    Lagrange basis at the Gauss points (If) and the basis derivatives at each
+    face's Gauss points (Drg, Dsg), for the metric terms there."""
+
+    def __init__(self, P: int):
+        R = ref(P)
+        self.P = P
+        n = cubature_points_per_direction(P)
+        self.rq, self.sq, self.wq = triangle_cubature(n)
+        self.ncub = self.wq.size
+        self.Icub = vandermonde(P, self.rq, self.sq) @ R.Vinv
+        Vr, Vs = grad_vandermonde(P, self.rq, self.sq)
+        self.Drc, self.Dsc = Vr @ R.Vinv, Vs @ R.Vinv
+        self.tg, self.wg = special.roots_legendre(n)
+        self.ng = n
+        tn = R.face_parameters()[0]                       # the same LGL parameters on every face
+        V1n = np.stack([jacobi_normalized(tn, 0, 0, m) for m in range(R.Nfp)], axis=1)
+        V1g = np.stack([jacobi_normalized(self.tg, 0, 0, m) for m in range(R.Nfp)], axis=1)
+        self.If = V1g @ np.linalg.inv(V1n)
+        t = self.tg
+        face_rs = [(t, -np.ones_like(t)), (-t, t), (-np.ones_like(t), -t)]
+        Drg, Dsg = [], []
+        for rg, sg in face_rs:
+            a, b = grad_vandermonde(P, rg, sg)
+            Drg.append(a @ R.Vinv)
+            Dsg.append(b @ R.Vinv)
+        self.Drg, self.Dsg = np.stack(Drg), np.stack(Dsg)
+        self.face_rs = face_rs
+
+
+@functools.lru_cache(maxsize=None)
+def weak_ops(P: int) -> WeakOperators:
+    return WeakOperators(P)
+
