@@ -60,6 +60,8 @@ enum dg_status {
     DG_EBUSY = -6        /* batch admission: no free slot, or over the HBM budget */
 };
 
+/* There is no separate DG_FP64 = 1 (FP64 state on the FP64 matrix cores):
+ * FP64 handles use DG_FP64_PLAIN, whose contractions run on the VALUs. */
 enum dg_precision {
     DG_FP64_PLAIN = 0,   /* FP64 throughout; straightforward VALU kernels */
     DG_FP32 = 2,         /* FP32 state and fused stage kernel; FP64 setup,
@@ -72,6 +74,12 @@ enum dg_precision {
 };
 
 enum dg_bc { DG_BC_INTERIOR = 0, DG_BC_WALL = 1, DG_BC_FARFIELD = 2 };
+
+/* Numerical flux at element faces (Section 2, after eq. weak_dg: local
+ * Lax-Friedrichs, or HLLC, which the paper reports to behave alike).
+ * HLLC: Davis wave-speed estimates and the star states of Toro, Spruce and
+ * Speares, evaluated in the frame of the face normal. */
+enum dg_riemann { DG_RIEMANN_LF = 0, DG_RIEMANN_HLLC = 1 };
 
 /* Message of the last error on this thread ("" if none). */
 const char *dg_last_error(void);
@@ -111,6 +119,7 @@ typedef struct {
     double av_eps0;               /* eps_max = av_eps0 * h_k / P */
     double av_s0;                 /* ramp centre; NaN: -4 log10 P */
     double av_kappa;              /* ramp half-width, > 0 */
+    int riemann;                  /* enum dg_riemann */
 } dg_mesh_desc;
 
 typedef struct dg_mesh dg_mesh;   /* opaque handle */
@@ -131,10 +140,15 @@ typedef struct {
  * isoparametric map per node, Section 2; face normals, sJ, Fscale per face
  * node).  Checks: 1 <= P <= 5, K >= 1, reciprocal connectivity
  * (EToE[EToE[k][f]][EToF[k][f]] = k), valid bc codes, J > 0 at every node
- * (else DG_EGEOM), n- = -n+ within 1e-8 at interior face nodes (else
- * DG_EGEOM).  Synchronises the stream.  *out is NULL on error. */
+ * (else DG_EGEOM), n- = -n+ within 1e-10 at interior face nodes (else
+ * DG_EGEOM).  Viscous handles also allocate here the scratch of dg_rhs and
+ * dg_viscosity, so that those calls allocate nothing.  Synchronises the
+ * stream.  *out is NULL on error. */
 int dg_mesh_setup(const dg_mesh_desc *desc, void *stream, dg_mesh **out);
 
+/* Wait for the work the handle's last call enqueued (on the stream it was
+ * given; work the caller enqueued elsewhere is not waited for), then free
+ * the handle's device tables. */
 int dg_mesh_destroy(dg_mesh *mesh);
 
 /* Bytes of one state array [K][4][Np] and of the work buffer that
@@ -143,7 +157,9 @@ int dg_buffer_bytes(const dg_mesh *mesh, size_t *state_bytes, size_t *work_bytes
 
 /* rhs = dU/dt for state U (device pointers, [K][4][Np]).  t is accepted for
  * interface completeness; the boundary data are time-independent.
- * Enqueues only. */
+ * Enqueues only (no allocation; may be captured into a graph).  Viscous
+ * handles use the handle's own scratch, so two dg_rhs calls on one handle
+ * must not overlap on different streams. */
 int dg_rhs(dg_mesh *mesh, const void *U, void *rhs, double t, void *stream);
 
 /* One LSERK(5,4) step of U in place.  dt > 0: that step; dt <= 0: the CFL
@@ -156,9 +172,11 @@ int dg_step(dg_mesh *mesh, void *U, void *work, double dt, void *stream);
  * and fills *stats (may be NULL).  Returns DG_ENONFINITE if the state
  * became non-finite, rho <= 0 or p <= 0 at any step.  FP32 handles take
  * the CFL bound from the stage kernels themselves (without viscosity: the
- * last stage, for the next step; with viscosity: the first stage's sensor),
- * in FP32 per face node with dt formed in FP64; FP64 handles and dg_step
- * use the FP64 reduction. */
+ * last stage, for the next step, and a kernel with the same per-node
+ * arithmetic before the first step; with viscosity: the first stage's
+ * sensor), evaluated in FP64 per node from the FP32 state; FP64 handles
+ * and dg_step use the FP64 reduction.  Calls compose: dg_run of N steps
+ * twice gives the same bits as one dg_run of 2N steps. */
 int dg_run(dg_mesh *mesh, void *U, void *work, int nsteps, dg_run_stats *stats, void *stream);
 
 /* Conserved totals sum_k sum_i w_ki U_ki, w_ki = sum_j M_ij J_kj, in FP64
@@ -170,8 +188,22 @@ int dg_totals(dg_mesh *mesh, const void *U, double out[4], void *stream);
 int dg_residual(dg_mesh *mesh, const void *U, void *work, double out[4], void *stream);
 
 /* Element viscosities eps_k of state U (device out [K] doubles).  Enqueues
- * only.  Returns DG_EINVAL if the mesh was set up without viscosity. */
+ * only (FP32 handles use scratch allocated at setup).  Returns DG_EINVAL if
+ * the mesh was set up without viscosity. */
 int dg_viscosity(dg_mesh *mesh, const void *U, double *eps, void *stream);
+
+/* p-refinement (Section 5, the p-refinement paragraph): the prolongation
+ * operator from order P to order Q >= P (host, row-major Np(Q) x Np(P)),
+ * I = V_Q[:, :Np(P)] V_P^{-1}: the degree-P polynomial evaluated at the
+ * order-Q nodes, which is the zero padding of its hierarchical modal
+ * coefficients (the first Np(P) modes of order Q's basis span degree <= P). */
+int dg_prolong_operator(int P, int Q, double *I);
+
+/* U_to = I U_from per element and field, from the state of handle `from`
+ * (order P) to that of handle `to` (order Q >= P); the two handles must
+ * describe the same elements (same K, same precision).  Device pointers
+ * [K][4][Np(P)] and [K][4][Np(Q)].  Enqueues only. */
+int dg_prolong(const dg_mesh *from, const void *U_from, const dg_mesh *to, void *U_to, void *stream);
 
 /* Replay of captured steps.  With graphs enabled (the default), dg_run on
  * an FP32 handle (with or without artificial viscosity) captures two steps
@@ -227,7 +259,10 @@ int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *by
  * running start at the next call. */
 typedef struct dg_batch dg_batch;
 
+/* A batch takes handles of any precision (each handle's own); there is no
+ * per-batch precision argument. */
 int dg_batch_create(size_t hbm_budget_bytes, int max_slots, dg_batch **out);
+/* Waits for the batch's last advance, then frees its tables. */
 int dg_batch_destroy(dg_batch *batch);
 
 /* Admit a solve of nsteps CFL steps.  DG_EBUSY if no slot is free or the

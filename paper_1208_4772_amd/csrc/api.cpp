@@ -42,7 +42,14 @@ struct dg_mesh {
     int precision = DG_FP64_PLAIN;
     size_t elem_bytes = 8;
     std::vector<void *> allocs;
-    double *eps64_scratch = nullptr;
+    // viscous handles: scratch of a pure rhs evaluation (viscosity [K] then
+    // sigma grad U, 2x state) and of dg_viscosity ([K]), separate so that
+    // the two calls may run on different streams; allocated at setup
+    char *rhs_scratch = nullptr;
+    void *visc_scratch = nullptr;
+    // recorded at the end of every call that enqueues work on a stream that
+    // is not being captured; dg_mesh_destroy waits for it
+    hipEvent_t done = nullptr;
 
     template <typename T>
     int alloc(T **p, size_t count) {
@@ -64,6 +71,7 @@ struct dg_mesh {
     }
     size_t owned_bytes = 0;
     ~dg_mesh() {
+        if (done) (void)hipEventDestroy(done);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -122,6 +130,13 @@ struct dg_mesh {
     size_t off_Q() const { return 3 * align256(state_bytes()); }
     size_t off_eps() const { return off_Q() + (dm.av ? align256(2 * state_bytes()) : 0); }
     size_t work_bytes() const { return off_eps() + (dm.av ? align256(size_t(dm.K) * elem_bytes) : 0); }
+    // mark the end of this call's work on st (not while st is capturing:
+    // the event would become a graph node)
+    void mark(hipStream_t st) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+            (void)hipEventRecord(done, st);
+    }
 };
 
 extern "C" {
@@ -170,6 +185,8 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     if (!d->EToE || !d->EToF || !d->bc || !d->x || !d->y) return fail(DG_EINVAL, "null mesh array");
     if (d->av_enable && (!(d->av_kappa > 0.0) || !(d->av_eps0 >= 0.0)))
         return fail(DG_EINVAL, "av_kappa must be > 0 and av_eps0 >= 0");
+    if (d->riemann != DG_RIEMANN_LF && d->riemann != DG_RIEMANN_HLLC)
+        return fail(DG_EINVAL, "riemann must be DG_RIEMANN_LF or DG_RIEMANN_HLLC");
     const int K = d->K, P = d->P;
     RefOps ref;
     if (!build_reference(P, ref)) return fail(DG_EINVAL, "reference element construction failed");
@@ -218,6 +235,7 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     dm.fp32 = d->precision == DG_FP32 || d->precision == DG_FP32_BF16X3;
     dm.bf3 = d->precision == DG_FP32_BF16X3;
     dm.av = d->av_enable != 0;
+    dm.riemann = d->riemann;
     dm.gamma = d->gamma;
     dm.cfl = d->cfl;
     for (int c = 0; c < 4; ++c) dm.qinf[c] = d->freestream[c];
@@ -372,6 +390,18 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         }
         SETUP_TRY(hipStreamSynchronize(st));
     }
+    if (dm.av) {
+        char *rs;
+        const size_t rbytes = align256(size_t(K) * m->elem_bytes) + 2 * m->state_bytes();
+        if ((rc = m->alloc(&rs, rbytes))) return cleanup(rc);
+        m->rhs_scratch = rs;
+        if (dm.fp32) {
+            float *vs;
+            if ((rc = m->alloc(&vs, size_t(K)))) return cleanup(rc);
+            m->visc_scratch = vs;
+        }
+    }
+    SETUP_TRY(hipEventCreateWithFlags(&m->done, hipEventDisableTiming));
     *out = m;
     g_err.clear();
     return DG_OK;
@@ -380,7 +410,8 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
 
 int dg_mesh_destroy(dg_mesh *m) {
     if (!m) return fail(DG_EINVAL, "mesh is NULL");
-    (void)hipDeviceSynchronize();
+    // the handle's last enqueued work (other streams are not waited for)
+    if (m->done) (void)hipEventSynchronize(m->done);
     delete m;
     return DG_OK;
 }
@@ -414,23 +445,17 @@ int dg_rhs(dg_mesh *m, const void *U, void *rhs, double t, void *stream) {
     if (U == rhs) return fail(DG_EINVAL, "U and rhs must not alias");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (m->dm.av) {
-        // viscosity scratch for a pure rhs evaluation
-        if (!m->eps64_scratch) {
-            void *q = nullptr;
-            size_t bytes = align256(size_t(m->dm.K) * m->elem_bytes) + 2 * m->state_bytes();
-            if (hipMalloc(&q, bytes) != hipSuccess) return fail(DG_ENOMEM, "rhs scratch allocation failed");
-            m->allocs.push_back(q);
-            m->eps64_scratch = static_cast<double *>(q);
-        }
-        char *base = reinterpret_cast<char *>(m->eps64_scratch);
+        // the handle's own scratch for the viscosity and sigma grad U
+        char *base = m->rhs_scratch;
         void *eps = base;
         void *Q = base + align256(size_t(m->dm.K) * m->elem_bytes);
         HIP_TRY(launch_sensor(m->dm, U, eps, st));
         HIP_TRY(launch_avgrad(m->dm, U, eps, Q, st));
         HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, rhs, 0, eps, Q, st));
-        return DG_OK;
+    } else {
+        HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, rhs, 0, nullptr, nullptr, st));
     }
-    HIP_TRY(launch_stage(m->dm, U, nullptr, nullptr, rhs, 0, nullptr, nullptr, st));
+    m->mark(st);
     return DG_OK;
 }
 
@@ -523,6 +548,37 @@ static int ensure_step_graph(dg_mesh *m, void *U, void *work) {
     return DG_OK;
 }
 
+int dg_prolong_operator(int P, int Q, double *I) {
+    if (P < 1 || Q > 5 || Q < P) return fail(DG_EINVAL, "need 1 <= P <= Q <= 5");
+    if (!I) return fail(DG_EINVAL, "I is NULL");
+    RefOps a, b;
+    if (!build_reference(P, a) || !build_reference(Q, b)) return fail(DG_EINVAL, "reference element construction failed");
+    for (int i = 0; i < b.Np; ++i)
+        for (int j = 0; j < a.Np; ++j) {
+            double v = 0.0;
+            for (int n = 0; n < a.Np; ++n) v += b.V[i * b.Np + n] * a.Vinv[n * a.Np + j];
+            I[i * a.Np + j] = v;
+        }
+    return DG_OK;
+}
+
+int dg_prolong(const dg_mesh *from, const void *U_from, const dg_mesh *to, void *U_to, void *stream) {
+    if (!from || !to) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U_from, "U_from")) return rc;
+    if (int rc = check_ptr(U_to, "U_to")) return rc;
+    if (from->dm.K != to->dm.K) return fail(DG_EINVAL, "the two handles have different element counts");
+    if (to->dm.P < from->dm.P) return fail(DG_EINVAL, "the target order is lower than the source order");
+    if (from->elem_bytes != to->elem_bytes) return fail(DG_EINVAL, "the two handles differ in state precision");
+    if (U_from == U_to) return fail(DG_EINVAL, "U_from and U_to must not alias");
+    const int np = from->dm.Np, nq = to->dm.Np;
+    std::vector<double> I(size_t(np) * nq);
+    if (int rc = dg_prolong_operator(from->dm.P, to->dm.P, I.data())) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_prolong(from->dm.K, np, nq, I.data(), to->dm.fp32, U_from, U_to, st));
+    const_cast<dg_mesh *>(to)->mark(st);
+    return DG_OK;
+}
+
 int dg_set_graphs(dg_mesh *m, int enable) {
     if (!m) return fail(DG_EINVAL, "mesh is NULL");
     m->graphs = enable != 0;
@@ -533,7 +589,10 @@ int dg_step(dg_mesh *m, void *U, void *work, double dt, void *stream) {
     if (!m) return fail(DG_EINVAL, "mesh is NULL");
     if (int rc = check_ptr(U, "U")) return rc;
     if (int rc = check_ptr(work, "work")) return rc;
-    return step_impl(m, U, work, dt, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (int rc = step_impl(m, U, work, dt, st)) return rc;
+    m->mark(st);
+    return DG_OK;
 }
 
 int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, void *stream) {
@@ -585,6 +644,7 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
     int flag = 0;
     HIP_TRY(hipMemcpyAsync(scal, m->dm.scal, sizeof(scal), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(&flag, m->dm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    m->mark(st);
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(m->time_collect());
     float ms = 0.f;
@@ -647,18 +707,12 @@ int dg_viscosity(dg_mesh *m, const void *U, double *eps, void *stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (m->dm.fp32) {
         // state-precision scratch, then widen into the caller's doubles
-        if (!m->eps64_scratch) {
-            void *q = nullptr;
-            size_t bytes = align256(size_t(m->dm.K) * m->elem_bytes) + 2 * m->state_bytes();
-            if (hipMalloc(&q, bytes) != hipSuccess) return fail(DG_ENOMEM, "scratch allocation failed");
-            m->allocs.push_back(q);
-            m->eps64_scratch = static_cast<double *>(q);
-        }
-        HIP_TRY(launch_sensor(m->dm, U, m->eps64_scratch, st));
-        HIP_TRY(launch_eps_to_double(m->dm, m->eps64_scratch, eps, st));
+        HIP_TRY(launch_sensor(m->dm, U, m->visc_scratch, st));
+        HIP_TRY(launch_eps_to_double(m->dm, m->visc_scratch, eps, st));
     } else {
         HIP_TRY(launch_sensor(m->dm, U, eps, st));
     }
+    m->mark(st);
     return DG_OK;
 }
 
@@ -836,7 +890,9 @@ struct dg_batch {
     long epoch_steps = 0;          // steps since the tables were last built
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
+    hipEvent_t done = nullptr;     // end of the last advance's work; destroy waits for it
     ~dg_batch() {
+        if (done) (void)hipEventDestroy(done);
         if (graph) (void)hipGraphExecDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (Group &g : groups) {
@@ -1003,6 +1059,10 @@ int dg_batch_create(size_t hbm_budget_bytes, int max_slots, dg_batch **out) {
     *out = nullptr;
     if (max_slots < 1) return fail(DG_EINVAL, "max_slots must be >= 1");
     dg_batch *b = new dg_batch();
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(DG_EDEVICE, "hipEventCreateWithFlags failed");
+    }
     b->budget = hbm_budget_bytes;
     b->slots.resize(max_slots);
     *out = b;
@@ -1011,7 +1071,8 @@ int dg_batch_create(size_t hbm_budget_bytes, int max_slots, dg_batch **out) {
 
 int dg_batch_destroy(dg_batch *b) {
     if (!b) return fail(DG_EINVAL, "batch is NULL");
-    (void)hipDeviceSynchronize();
+    // the batch's tables may still be read by its last advance
+    if (b->done) (void)hipEventSynchronize(b->done);
     delete b;
     return DG_OK;
 }
@@ -1116,6 +1177,9 @@ int dg_batch_advance(dg_batch *b, int max_steps, void *stream, int *steps_run) {
                     HIP_TRY(launch_cfl_vmax(s.mesh->dm, s.U, s.mesh->dm.vmax, st));
             }
         }
+    for (Slot &s : b->slots)
+        if (s.used) s.mesh->mark(st);
+    (void)hipEventRecord(b->done, st);
     if (steps_run) *steps_run = n;
     return DG_OK;
 }

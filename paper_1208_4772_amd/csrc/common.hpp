@@ -182,6 +182,95 @@ __device__ inline void lf_jump(T g, const T um[kFields], const T up[kFields], T 
     }
 }
 
+// HLLC state of side K behind its wave of speed SK, contact speed Ss:
+// rho_K (S_K - v_n)/(S_K - S*) (1, v + (S* - v_n) n,
+// E/rho + (S* - v_n)(S* + p / (rho (S_K - v_n)))).
+template <typename T>
+__device__ inline void hllc_star(const T u[kFields], T ir, T p, T vn, T nx, T ny, T SK, T Ss,
+                                 T out[kFields]) {
+    const T f = u[0] * (SK - vn) * rcp(SK - Ss);
+    const T dv = Ss - vn;
+    out[0] = f;
+    out[1] = f * (u[1] * ir + dv * nx);
+    out[2] = f * (u[2] * ir + dv * ny);
+    out[3] = f * (u[3] * ir + dv * (Ss + p * rcp(u[0] * (SK - vn))));
+}
+
+// n.F(u-) - F*(u-, u+) for the HLLC flux (Toro, Spruce and Speares), the
+// selectable alternative to local Lax-Friedrichs: Davis wave speeds
+// S_L = min(v_n- - c-, v_n+ - c+), S_R = max(v_n- + c-, v_n+ + c+), contact
+// speed S* from the two momentum balances; F* = n.F(u-) (S_L >= 0),
+// n.F(u-) + S_L (U*_L - u-) (S_L < 0 <= S*), n.F(u+) + S_R (U*_R - u+)
+// (S* < 0 < S_R), n.F(u+) (S_R <= 0).
+template <typename T>
+__device__ inline void hllc_jump(T g, const T um[kFields], const T up[kFields], T nx, T ny, T d[kFields]) {
+    T fm[kFields], fp[kFields], lm, lp;
+    normal_flux(g, um, nx, ny, fm, lm);
+    normal_flux(g, up, nx, ny, fp, lp);
+    const T irl = rcp(um[0]), irr = rcp(up[0]);
+    const T vnl = (um[1] * nx + um[2] * ny) * irl, vnr = (up[1] * nx + up[2] * ny) * irr;
+    const T pl = pressure_ir(g, um, irl), pr = pressure_ir(g, up, irr);
+    const T cl = fsqrt(g * pl * irl), cr = fsqrt(g * pr * irr);
+    const T SL = fmin(vnl - cl, vnr - cr), SR = fmax(vnl + cl, vnr + cr);
+    const T Ss = (pr - pl + um[0] * vnl * (SL - vnl) - up[0] * vnr * (SR - vnr)) *
+                 rcp(um[0] * (SL - vnl) - up[0] * (SR - vnr));
+    T us[kFields];
+    if (SL >= T(0)) {
+        for (int c = 0; c < kFields; ++c) d[c] = T(0);
+    } else if (Ss >= T(0)) {
+        hllc_star(um, irl, pl, vnl, nx, ny, SL, Ss, us);
+        for (int c = 0; c < kFields; ++c) d[c] = -SL * (us[c] - um[c]);
+    } else if (SR > T(0)) {
+        hllc_star(up, irr, pr, vnr, nx, ny, SR, Ss, us);
+        for (int c = 0; c < kFields; ++c) d[c] = fm[c] - (fp[c] + SR * (us[c] - up[c]));
+    } else {
+        for (int c = 0; c < kFields; ++c) d[c] = fm[c] - fp[c];
+    }
+}
+
+// Numerical-flux difference of the handle's choice: 0 local Lax-Friedrichs,
+// 1 HLLC.
+enum { RIEMANN_LF = 0, RIEMANN_HLLC = 1 };
+template <typename T>
+__device__ inline void flux_jump(int riemann, T g, const T um[kFields], const T up[kFields], T nx, T ny,
+                                 T d[kFields]) {
+    if (riemann == RIEMANN_HLLC)
+        hllc_jump(g, um, up, nx, ny, d);
+    else
+        lf_jump(g, um, up, nx, ny, d);
+}
+
+// Time-step bound of one face node (the paper's dt = O(p^-2) with the
+// viscous term; reading R11), always in FP64 whatever the state precision:
+// 1/2 (P+1)^2 Fscale (|v| + c) + 1/4 (P+1)^4 Fscale^2 eps.
+__device__ inline double cfl_bound(double g, const double u[kFields], double fs, double e, double P1) {
+    const double vx = u[1] / u[0], vy = u[2] / u[0];
+    const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * pressure(g, u) / u[0]);
+    return 0.5 * P1 * P1 * fs * lam + 0.25 * P1 * P1 * P1 * P1 * fs * fs * e;
+}
+
+// State check of one node in FP64: non-finite values, rho <= 0 or p <= 0.
+__device__ inline bool bad_state(double g, const double u[kFields]) {
+    const double p = pressure(g, u);
+    return !(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+           !isfinite(p);
+}
+
+// Viscous face-flux difference (sigma Q)*.n - (sigma Q)-.n at a slip wall.
+// gm[c] = n.(sigma- Q-) of field c.  The ghost gradient is the mirror image
+// implied by the mirror ghost state: mirroring flips a field's normal
+// derivative, so rho and E (mirrored unchanged) get (sigma Q)*.n = 0, and
+// the momentum (mirrored to m - 2 (m.n) n) keeps only the normal component
+// of its normal derivative, (sigma Q)*.n = (gm_m . n) n.
+template <typename T>
+__device__ inline void wall_visc_jump(const T gm[kFields], T nx, T ny, T d[kFields]) {
+    const T gn = gm[1] * nx + gm[2] * ny;
+    d[0] = -gm[0];
+    d[1] = gn * nx - gm[1];
+    d[2] = gn * ny - gm[2];
+    d[3] = -gm[3];
+}
+
 // Carpenter-Kennedy 2N-storage (5,4) coefficients.
 __host__ __device__ inline double rk_a(int s) {
     switch (s) {

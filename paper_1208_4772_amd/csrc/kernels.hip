@@ -25,6 +25,7 @@ constexpr int kBlock = 256;
 template <typename T>
 struct StageArgs {
     int K, stage, mode;
+    int riemann;   // numerical flux: RIEMANN_LF or RIEMANN_HLLC
     T g, ra, rb;
     FarField<T> ff;
     const T *__restrict__ Uin;
@@ -151,21 +152,29 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
             } else {
                 ghost_state(a.g, code, um, nx, ny, a.ff, up);
             }
-            lf_jump(a.g, um, up, nx, ny, d);
-            if (AV) {
+            flux_jump(a.riemann, a.g, um, up, nx, ny, d);
+            if (AV && code != BC_FARFIELD) {
+                // (sigma Q)*.n - (sigma Q)-.n: the central value inside, the
+                // mirror closure at a wall (wall_visc_jump), zero at the far
+                // field (the element's own value)
+                T vmv[kFields], vj[kFields];
 #pragma unroll
-                for (int c = 0; c < kFields; ++c) {
-                    T vmv = sig * (nx * a.Q[((k * 2 + 0) * kFields + c) * Np + vm] +
-                                   ny * a.Q[((k * 2 + 1) * kFields + c) * Np + vm]);
-                    T vstar = vmv;
-                    if (kn >= 0) {
-                        T sp = sqrt(a.eps[kn]);
+                for (int c = 0; c < kFields; ++c)
+                    vmv[c] = sig * (nx * a.Q[((k * 2 + 0) * kFields + c) * Np + vm] +
+                                    ny * a.Q[((k * 2 + 1) * kFields + c) * Np + vm]);
+                if (kn >= 0) {
+                    const T sp = sqrt(a.eps[kn]);
+#pragma unroll
+                    for (int c = 0; c < kFields; ++c) {
                         T vpv = sp * (nx * a.Q[((kn * 2 + 0) * kFields + c) * Np + vp] +
                                       ny * a.Q[((kn * 2 + 1) * kFields + c) * Np + vp]);
-                        vstar = T(0.5) * (vmv + vpv);
+                        vj[c] = T(0.5) * (vmv[c] + vpv) - vmv[c];
                     }
-                    d[c] += vstar - vmv;
+                } else {
+                    wall_visc_jump(vmv, nx, ny, vj);
                 }
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) d[c] += vj[c];
             }
 #pragma unroll
             for (int c = 0; c < kFields; ++c) sJ[el][c][q] = fs * d[c];
@@ -234,6 +243,7 @@ template <typename T>
 struct AvArgs {
     int K, P;
     T g;
+    double gamma;   // the time-step bound is formed in FP64
     FarField<T> ff;
     double s0, kappa;
     const T *__restrict__ U;
@@ -253,9 +263,8 @@ struct AvArgs {
 // Persson-Peraire sensor on the density: u_hat = V^{-1} rho, S = (energy of
 // the degree-P modes) / (total modal energy), s = log10 S, sine ramp of
 // half-width kappa around s0, capped at eps_max,k.  CFL: also the time-step
-// bound of the state with its new viscosity (FP32 arithmetic per face node,
-// like the stage kernel's fused bound), reduced into the block's slot, and
-// the state check (rho, p > 0, finite).
+// bound of the state with its new viscosity (FP64 per face node, cfl_bound),
+// reduced into the block's slot, and the state check (rho, p > 0, finite).
 template <typename T, int P, bool CFL>
 __device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) {
     using O = Order<P>;
@@ -263,7 +272,7 @@ __device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) 
     __shared__ T sR[EB][Np];
     __shared__ double sE[EB][Np];
     __shared__ T sEps[EB];
-    __shared__ float sRed[kBlock / 64];
+    __shared__ double sRed[kBlock / 64];
     // V^{-1} staged once per block: every thread reads a row of it, and
     // reading it through the caches costs a memory instruction per entry
     __shared__ T sVi[Np * Np];
@@ -301,44 +310,38 @@ __device__ __forceinline__ void sensor_body(const AvArgs<T> &a, const int tile) 
     }
     if constexpr (CFL) {
         __syncthreads();
-        float vmax = 0.f;
+        double vmax = 0.0;
         int bad = 0;
         if (t.act) {
             const T *Uk = a.U + t.k * kFields * Np;
             {
-                T u[kFields];
+                double u[kFields];
 #pragma unroll
-                for (int c = 0; c < kFields; ++c) u[c] = Uk[c * Np + t.i];
-                const T p = pressure(a.g, u);
-                if (!(u[0] > T(0)) || !(p > T(0)) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
-                    !isfinite(p))
-                    bad = 1;
+                for (int c = 0; c < kFields; ++c) u[c] = double(Uk[c * Np + t.i]);
+                if (bad_state(a.gamma, u)) bad = 1;
             }
-            const float P1 = P + 1.0f, e = float(sEps[t.el]);
+            const double P1 = P + 1.0, e = double(sEps[t.el]);
             for (int q = t.i; q < NF3; q += Np) {
                 const int v = face_node(P, q / Nfp, q % Nfp);
-                float u[kFields];
+                double u[kFields];
 #pragma unroll
-                for (int c = 0; c < kFields; ++c) u[c] = float(Uk[c * Np + v]);
-                const float ir = 1.0f / u[0];
-                const float vx = u[1] * ir, vy = u[2] * ir;
-                const float p = pressure(float(a.g), u);
-                const float lam = sqrtf(vx * vx + vy * vy) + sqrtf(float(a.g) * p * ir);
-                const float fs = float(a.fgeo[(t.k * 3 + 2) * NF3 + q]);
-                const float val = 0.5f * P1 * P1 * fs * lam + 0.25f * P1 * P1 * P1 * P1 * fs * fs * e;
-                vmax = fmaxf(vmax, val);
+                for (int c = 0; c < kFields; ++c) u[c] = double(Uk[c * Np + v]);
+                const double val = cfl_bound(a.gamma, u, double(a.fgeo[(t.k * 3 + 2) * NF3 + q]), e, P1);
+                vmax = val > vmax ? val : vmax;
             }
         }
         if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.flag, 1);
-        for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(vmax, off);
+            vmax = o > vmax ? o : vmax;
+        }
         if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = vmax;
         __syncthreads();
         if (threadIdx.x == 0) {
-            float m = sRed[0];
-            for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sRed[w]);
+            double m = sRed[0];
+            for (int w = 1; w < kBlock / 64; ++w) m = sRed[w] > m ? sRed[w] : m;
             // non-negative doubles order like their bit patterns
-            atomicMax(a.vmax + (blockIdx.x & (kVmaxSlots - 1)),
-                      (unsigned long long)__double_as_longlong(double(m)));
+            atomicMax(a.vmax + (blockIdx.x & (kVmaxSlots - 1)), (unsigned long long)__double_as_longlong(m));
         }
     }
 }
@@ -555,9 +558,14 @@ __global__ __launch_bounds__(kBlock) void k_geometry(int K, const double *__rest
     Tile<P> t(K);
     const long k = t.k;
     const int i = t.i, el = t.el;
+    // coordinates relative to the element's first node: Dr and Ds annihilate
+    // constants, so the metric terms are the same in exact arithmetic, but
+    // the sums no longer cancel the absolute position (on small elements far
+    // from the origin that cancellation costs ~|x| / h of the metric terms'
+    // precision)
     if (t.act) {
-        sX[el][i] = x[k * Np + i];
-        sY[el][i] = y[k * Np + i];
+        sX[el][i] = x[k * Np + i] - x[k * Np];
+        sY[el][i] = y[k * Np + i] - y[k * Np];
     }
     __syncthreads();
     if (t.act) {
@@ -632,7 +640,7 @@ __global__ void k_check_normals(int K, const int *__restrict__ nbr, const int *_
     const int qn = face_nbr_face(info, f) * Nfp + Nfp - 1 - j;
     const double ex = fgeo[(k * 3 + 0) * NF3 + q] + fgeo[(kn * 3 + 0) * NF3 + qn];
     const double ey = fgeo[(k * 3 + 1) * NF3 + q] + fgeo[(kn * 3 + 1) * NF3 + qn];
-    if (!(fabs(ex) <= 1e-8 && fabs(ey) <= 1e-8)) atomicAdd(count + 1, 1);
+    if (!(fabs(ex) <= 1e-10 && fabs(ey) <= 1e-10)) atomicAdd(count + 1, 1);
 }
 
 template <int P>
@@ -740,10 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_cfl(int K, double g, const T *__rest
             u[c] = double(U[(k * kFields + c) * Np + i]);
             sU[el][c][i] = u[c];
         }
-        const double p = pressure(g, u);
-        if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
-            !isfinite(p))
-            bad = 1;
+        if (bad_state(g, u)) bad = 1;
     }
     __syncthreads();
     double vmax = 0.0;
@@ -756,10 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_cfl(int K, double g, const T *__rest
             double u[kFields];
 #pragma unroll
             for (int c = 0; c < kFields; ++c) u[c] = sU[el][c][v];
-            const double vx = u[1] / u[0], vy = u[2] / u[0];
-            const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * pressure(g, u) / u[0]);
-            const double fs = fgeo64[(k * 3 + 2) * NF3 + q];
-            const double val = 0.5 * P1 * P1 * fs * lam + 0.25 * P1 * P1 * P1 * P1 * fs * fs * e;
+            const double val = cfl_bound(g, u, fgeo64[(k * 3 + 2) * NF3 + q], e, P1);
             if (val > vmax) vmax = val;
         }
     }
@@ -915,6 +917,7 @@ template <typename T>
 hipError_t stage_t(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                    const void *eps, const void *Q, hipStream_t st) {
     StageArgs<T> a;
+    a.riemann = m.riemann;
     a.K = m.K;
     a.stage = stage;
     a.mode = rhs ? 0 : 1;
@@ -950,6 +953,7 @@ AvArgs<T> av_args(const DevMesh &m) {
     a.K = m.K;
     a.P = m.P;
     a.g = T(m.gamma);
+    a.gamma = m.gamma;
     a.ff = make_farfield<T>(m.gamma, m.qinf);
     a.s0 = m.av_s0;
     a.kappa = m.av_kappa;
@@ -1122,6 +1126,7 @@ static hipError_t cfl_t(const DevMesh &m, const void *U, const void *eps, double
 }
 
 hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st) {
+    if (m.fp32) return launch_cfl_vmax_mfma(m, U, slot, st);
     hipError_t e = with_order(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         if (m.fp32)
@@ -1177,6 +1182,48 @@ static hipError_t residual_t(const DevMesh &m, const void *X, hipStream_t st) {
 
 hipError_t launch_residual(const DevMesh &m, const void *rhs, hipStream_t st) {
     return m.fp32 ? residual_t<float>(m, rhs, st) : residual_t<double>(m, rhs, st);
+}
+
+// Prolongation of a state of order P to order Q > P (p-refinement): the
+// degree-P polynomial of each element and field evaluated at the order-Q
+// nodes, U_Q = I U_P with I = V_Q[:, :Np(P)] V_P^{-1} (the hierarchical modes
+// of degree <= P are the first Np(P) of order Q's basis, so this is the
+// paper's zero padding of the modal coefficients).  One thread per output
+// value; the operator travels in the kernel arguments; sums in FP64.
+struct ProlongOp {
+    int np_from, np_to;
+    double I[kProlongMax];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(long n, ProlongOp op, const T *__restrict__ Uf,
+                                                    T *__restrict__ Ut) {
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= n) return;
+    const long row = idx / op.np_to;          // element * 4 + field
+    const int i = int(idx - row * op.np_to);
+    const T *src = Uf + row * op.np_from;
+    double acc = 0.0;
+    for (int j = 0; j < op.np_from; ++j) acc += op.I[i * op.np_from + j] * double(src[j]);
+    Ut[idx] = T(acc);
+}
+
+hipError_t launch_prolong(int K, int np_from, int np_to, const double *I, bool fp32, const void *Uf, void *Ut,
+                          hipStream_t st) {
+    if (np_from * np_to > kProlongMax) return hipErrorInvalidValue;
+    ProlongOp op;
+    op.np_from = np_from;
+    op.np_to = np_to;
+    for (int z = 0; z < np_from * np_to; ++z) op.I[z] = I[z];
+    const long n = long(K) * kFields * np_to;
+    const dim3 grid(unsigned((n + kBlock - 1) / kBlock)), block(kBlock);
+    if (fp32)
+        hipLaunchKernelGGL((k_prolong<float>), grid, block, 0, st, n, op, static_cast<const float *>(Uf),
+                           static_cast<float *>(Ut));
+    else
+        hipLaunchKernelGGL((k_prolong<double>), grid, block, 0, st, n, op, static_cast<const double *>(Uf),
+                           static_cast<double *>(Ut));
+    return hipGetLastError();
 }
 
 hipError_t launch_eps_to_double(const DevMesh &m, const void *eps, double *out, hipStream_t st) {

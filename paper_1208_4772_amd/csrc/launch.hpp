@@ -28,6 +28,7 @@ struct DevMesh {
     bool fp32 = false;
     bool bf3 = false;              // FP32 handle whose stage product runs as BF16x3
     bool av = false;
+    int riemann = 0;               // numerical flux: 0 local Lax-Friedrichs, 1 HLLC
     double gamma = 1.4, cfl = 0.5;
     double qinf[4] = {1, 0, 0, 2.5};
     double av_s0 = 0, av_kappa = 1;
@@ -106,8 +107,13 @@ void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int 
 int mfma_tiles(const DevMesh &m);
 hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items, int nitems,
                                    hipStream_t st);
-// CFL bound of state U (FP64) into *slot as a bit pattern; raises *flag on bad states
+// CFL bound of state U (FP64) into the kVmaxSlots slots at *slot as bit
+// patterns (the maximum over them is the bound); raises *flag on bad states.
+// FP32 handles take the matrix-core kernel's own per-node bound
+// (launch_cfl_vmax_mfma), so that a run's first step sees what a fused last
+// stage would have left.
 hipError_t launch_cfl_vmax(const DevMesh &m, const void *U, unsigned long long *slot, hipStream_t st);
+hipError_t launch_cfl_vmax_mfma(const DevMesh &m, const void *U, unsigned long long *slots, hipStream_t st);
 size_t mfma_opsA_floats(int P);
 void mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, float *out);
 size_t mfma_opsB_words(int P);
@@ -152,5 +158,9 @@ hipError_t launch_residual(const DevMesh &m, const void *rhs, hipStream_t st);
 // eps (state precision) -> double
 hipError_t launch_eps_to_double(const DevMesh &m, const void *eps, double *out, hipStream_t st);
 hipError_t launch_reset_scalars(const DevMesh &m, hipStream_t st);
+// p-refinement: U_to [K][4][np_to] = I (np_to x np_from, row-major, host) U_from
+constexpr int kProlongMax = 21 * 21;
+hipError_t launch_prolong(int K, int np_from, int np_to, const double *I, bool fp32, const void *Uf, void *Ut,
+                          hipStream_t st);
 
 }  // namespace dg

@@ -25,8 +25,8 @@
 // blocks share a CU and hide each other's memory latency.
 //
 // Time step: in a fused run without viscosity the last stage also reduces
-// the CFL bound of the new state (FP32 per node, exact maximum) into
-// device slots, and the next step's first stage turns it into dt (FP64), so
+// the CFL bound of the new state (FP64 per node from the FP32 state, exact
+// maximum) into device slots, and the next step's first stage turns it into dt (FP64), so
 // a step needs no separate reduction launches; with viscosity the first
 // stage's sensor fills the slots instead (it knows the new viscosity).
 #include <hip/hip_runtime.h>
@@ -74,6 +74,7 @@ struct MShape {
 
 struct MfmaArgs {
     int K, stage, mode, nblocks, chunk;
+    int riemann;     // numerical flux: RIEMANN_LF or RIEMANN_HLLC
     int cfl_mode;    // 1: this (first) stage turns *vmax_in into dt
     int cfl_accum;   // 1: this (last) stage reduces the new state's CFL bound into *vmax_out
     float g, ra, rb;
@@ -138,17 +139,22 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
     } else {
         ghost_state(a.g, code, um, nx, ny, a.ff, up);
     }
-    // local Lax-Friedrichs: n.F(U-) - F* = (n.F(U-) - n.F(U+)) / 2 + lam (U+ - U-) / 2
-    float fm[4], fp[4], lm, lp;
-    normal_flux(a.g, um, nx, ny, fm, lm);
-    normal_flux(a.g, up, nx, ny, fp, lp);
-    const float lam = lm > lp ? lm : lp;
+    if (a.riemann == RIEMANN_HLLC) {
+        hllc_jump(a.g, um, up, nx, ny, d);
+    } else {
+        // local Lax-Friedrichs: n.F(U-) - F* = (n.F(U-) - n.F(U+)) / 2 + lam (U+ - U-) / 2
+        float fm[4], fp[4], lm, lp;
+        normal_flux(a.g, um, nx, ny, fm, lm);
+        normal_flux(a.g, up, nx, ny, fp, lp);
+        const float lam = lm > lp ? lm : lp;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
+        for (int c = 0; c < 4; ++c) d[c] = 0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]);
+    }
     if constexpr (AV) {
-        // viscous face term with the central flux: (sigma Q)* . n - (sigma Q)- . n,
-        // (sigma Q)* the mean of both sides inside, the interior value on a
-        // boundary (so no contribution there)
+        // viscous face term (sigma Q)* . n - (sigma Q)- . n: (sigma Q)* the
+        // mean of both sides inside, the mirror closure at a slip wall
+        // (wall_visc_jump), the interior value at the far field (so no
+        // contribution there)
         if (code == BC_INTERIOR) {
             const int j = q - f * Nfp;
             const long km = k0 + el;
@@ -162,10 +168,49 @@ __device__ __forceinline__ void face_task(const MfmaArgs &a, const long k0, cons
                 const float vpv = sp * (nx * Qp[c * Np + vp] + ny * Qp[(4 + c) * Np + vp]);
                 d[c] += 0.5f * (vmv + vpv) - vmv;
             }
+        } else if (code == BC_WALL) {
+            const long km = k0 + el;
+            const float sm = fsqrt(a.eps[km]);
+            const float *Qm = a.Q + km * 8 * Np;
+            float vmv[4], vj[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) vmv[c] = sm * (nx * Qm[c * Np + vm] + ny * Qm[(4 + c) * Np + vm]);
+            wall_visc_jump(vmv, nx, ny, vj);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) d[c] += vj[c];
         }
     }
     const f32x4 jv = {fs * d[0], fs * d[1], fs * d[2], fs * d[3]};
     *reinterpret_cast<f32x4 *>(&sBflat[((el >> 2) * KP + 2 * Np + q) * 16 + (el & 3) * 4]) = jv;
+}
+
+// Time-step bound and state check of node `in` of an element of an FP32
+// matrix-core handle: the state widened to FP64, its wave speed times the
+// largest Fscale of the faces the node lies on (the element's FP32 record:
+// g16[6 + 3 f] for an affine element, the per-face-node values of its curved
+// record gc otherwise), all in FP64 (cfl_bound).
+template <int P>
+__device__ __forceinline__ double node_cfl(double gamma, const float (&uf)[4], int in, const float *g16,
+                                           const float *gc, int &bad) {
+    constexpr int Np = (P + 1) * (P + 2) / 2, Nfp = P + 1, NF3 = 3 * Nfp;
+    double u[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = double(uf[c]);
+    if (bad_state(gamma, u)) bad = 1;
+    constexpr NodeFaceTable<P> kNF;
+    const int nq = kNF.v[in];
+    if (!nq) return 0.0;
+    const int q0 = (nq & 255) - 1, q1 = (nq >> 8) - 1;
+    float fs;
+    if (!gc) {
+        fs = g16[6 + 3 * (q0 / Nfp)];
+        if (q1 >= 0) fs = fmaxf(fs, g16[6 + 3 * (q1 / Nfp)]);
+    } else {
+        const float *gf = gc + 4 * Np + 2 * NF3;
+        fs = gf[q0];
+        if (q1 >= 0) fs = fmaxf(fs, gf[q1]);
+    }
+    return cfl_bound(gamma, u, double(fs), 0.0, P + 1.0);
 }
 
 // One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
@@ -196,7 +241,7 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
     __shared__ float sU[TF];
     __shared__ float sB[NT][KP][16];    // B operand; afterwards the result of that column group
     __shared__ float sG[EB][16];
-    __shared__ float sRed[W];
+    __shared__ double sRed[W];
     __shared__ int sFN[NF3];              // face node ids, face-major, counter-clockwise
 
     const int tid = threadIdx.x;
@@ -506,51 +551,82 @@ __device__ __forceinline__ void stage_tile(const MfmaArgs &a, const int tile) {
         }
     }
     if (a.cfl_accum) {
-        // CFL bound and state check of the new state: one lane per node; the
-        // node's wave speed times the largest Fscale of the faces it lies on
-        // (FP32 like the state; the maximum is exact and dt = cfl / max is
-        // formed in FP64 by the next step's first stage)
+        // CFL bound and state check of the new state: one lane per node
+        // (node_cfl), reduced into the block's slot; the next step's first
+        // stage turns the maximum into dt
         __syncthreads();
-        float vmax_lane = 0.f;
+        double vmax_lane = 0.0;
         int bad = 0;
         if (node_ok) {
             float u[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) u[c] = sU[(eln * 4 + c) * Np + in];
-            const float ir = rcp(u[0]);
-            const float vx = u[1] * ir, vy = u[2] * ir;
-            const float p = pressure_ir(a.g, u, ir);
-            if (!(u[0] > 0.f) || !(p > 0.f) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
-                !isfinite(p))
-                bad = 1;
-            constexpr NodeFaceTable<P> kNF;
-            const int nq = kNF.v[in];
-            if (nq) {
-                const int q0 = (nq & 255) - 1, q1 = (nq >> 8) - 1;
-                float fs;
-                if (!curved_lane) {
-                    fs = sG[eln][6 + 3 * (q0 / Nfp)];
-                    if (q1 >= 0) fs = fmaxf(fs, sG[eln][6 + 3 * (q1 / Nfp)]);
-                } else {
-                    const float *gf = a.geoC + (long)a.cidx[k0 + eln] * (4 * Np + 9 * Nfp) + 4 * Np + 2 * NF3;
-                    fs = gf[q0];
-                    if (q1 >= 0) fs = fmaxf(fs, gf[q1]);
-                }
-                const float lam = fsqrt(vx * vx + vy * vy) + fsqrt(a.g * p * ir);
-                vmax_lane = 0.5f * float((P + 1) * (P + 1)) * fs * lam;
-            }
+            const float *gc = curved_lane ? a.geoC + (long)a.cidx[k0 + eln] * (4 * Np + 9 * Nfp) : nullptr;
+            vmax_lane = node_cfl<P>(a.gamma, u, in, &sG[eln][0], gc, bad);
         }
         if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
-        for (int off = 32; off > 0; off >>= 1) vmax_lane = fmaxf(vmax_lane, __shfl_xor(vmax_lane, off));
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(vmax_lane, off);
+            vmax_lane = o > vmax_lane ? o : vmax_lane;
+        }
         if (lane == 0) sRed[wave] = vmax_lane;
         __syncthreads();
         if (tid == 0) {
-            float m = sRed[0];
-            for (int w = 1; w < W; ++w) m = fmaxf(m, sRed[w]);
-            // a NaN speed leaves m unordered; the flag above reports it
-            atomicMax(a.vmax_out + (blockIdx.x & (kVmaxSlots - 1)),
-                      (unsigned long long)__double_as_longlong(double(m)));
+            double m = sRed[0];
+            for (int w = 1; w < W; ++w) m = sRed[w] > m ? sRed[w] : m;
+            // non-negative doubles order like their bit patterns
+            atomicMax(a.vmax_out + (blockIdx.x & (kVmaxSlots - 1)), (unsigned long long)__double_as_longlong(m));
         }
+    }
+}
+
+// First-step CFL bound of a matrix-core handle: the same node_cfl over every
+// node of the state, reduced into the slots (which the caller has zeroed),
+// so that a run's first step takes the bound a fused last stage would have
+// left (dg_run(N) twice equals dg_run(2N)).
+template <int P>
+__global__ __launch_bounds__(256) void k_cfl_vmax_mfma(int K, double gamma, const float *__restrict__ U,
+                                                       const int4 *__restrict__ conn,
+                                                       const float4 *__restrict__ geoA,
+                                                       const int *__restrict__ cidx,
+                                                       const float *__restrict__ geoC,
+                                                       unsigned long long *__restrict__ slots,
+                                                       int *__restrict__ flag) {
+    constexpr int Np = (P + 1) * (P + 2) / 2, Nfp = P + 1;
+    __shared__ double sRed[4];
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const long k = idx / Np;
+    const int in = int(idx - k * Np);
+    double v = 0.0;
+    int bad = 0;
+    if (k < K) {
+        float u[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) u[c] = U[(k * 4 + c) * Np + in];
+        float g16[16];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+            const float4 r = geoA[k * 4 + z];
+            g16[4 * z] = r.x;
+            g16[4 * z + 1] = r.y;
+            g16[4 * z + 2] = r.z;
+            g16[4 * z + 3] = r.w;
+        }
+        const bool curved = (conn[k].w & kCurvedBit) != 0;
+        const float *gc = curved ? geoC + (long)cidx[k] * (4 * Np + 9 * Nfp) : nullptr;
+        v = node_cfl<P>(gamma, u, in, g16, gc, bad);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sRed[0];
+        for (int w = 1; w < 4; ++w) m = sRed[w] > m ? sRed[w] : m;
+        atomicMax(slots + (blockIdx.x & (kVmaxSlots - 1)), (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -729,6 +805,7 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
                           const void *Q = nullptr) {
     MfmaArgs a;
     a.K = m.K;
+    a.riemann = m.riemann;
     a.stage = stage;
     a.mode = rhs ? 0 : 1;
     a.cfl_mode = step.cfl_mode;
@@ -795,6 +872,21 @@ hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, c
             hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, true>), grid, block, 0, st, j, it, nitems, chunk);
         else
             hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, false>), grid, block, 0, st, j, it, nitems, chunk);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_cfl_vmax_mfma(const DevMesh &m, const void *U, unsigned long long *slots, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(slots, 0, kVmaxSlots * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    return with_order_m(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        constexpr int Np = (P + 1) * (P + 2) / 2;
+        const long nodes = long(m.K) * Np;
+        const dim3 grid(unsigned((nodes + 255) / 256)), block(256);
+        hipLaunchKernelGGL((k_cfl_vmax_mfma<P>), grid, block, 0, st, m.K, m.gamma,
+                           static_cast<const float *>(U), reinterpret_cast<const int4 *>(m.conn4),
+                           reinterpret_cast<const float4 *>(m.geoA), m.cidx, m.geoC, slots, m.flag);
         return hipGetLastError();
     });
 }

@@ -22,6 +22,8 @@ DG_OK, DG_EINVAL, DG_ENOMEM, DG_EGEOM, DG_ENONFINITE, DG_EDEVICE, DG_EBUSY = 0, 
 DG_FP64_PLAIN, DG_FP32, DG_FP32_BF16X3 = 0, 2, 3
 PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP32,
               "bf16x3": DG_FP32_BF16X3}
+DG_RIEMANN_LF, DG_RIEMANN_HLLC = 0, 1
+RIEMANN = {"lf": DG_RIEMANN_LF, "hllc": DG_RIEMANN_HLLC}
 
 # Every symbol include/dg.h declares.
 EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
@@ -30,7 +32,7 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_autotune", "dg_mesh_footprint",
            "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
-           "dg_status")
+           "dg_status", "dg_prolong_operator", "dg_prolong")
 
 
 class DGError(RuntimeError):
@@ -46,7 +48,7 @@ class MeshDesc(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p),
                 ("freestream", C.c_double * 4),
                 ("av_enable", C.c_int), ("av_eps0", C.c_double), ("av_s0", C.c_double),
-                ("av_kappa", C.c_double)]
+                ("av_kappa", C.c_double), ("riemann", C.c_int)]
 
 
 class RunStats(C.Structure):
@@ -81,6 +83,8 @@ def lib():
         L.dg_buffer_bytes.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.dg_rhs.argtypes = [vp, vp, vp, d, vp]
         L.dg_step.argtypes = [vp, vp, vp, d, vp]
+        L.dg_prolong_operator.argtypes = [i, i, vp]
+        L.dg_prolong.argtypes = [vp, vp, vp, vp, vp]
         L.dg_run.argtypes = [vp, vp, vp, i, C.POINTER(RunStats), vp]
         L.dg_totals.argtypes = [vp, vp, vp, vp]
         L.dg_residual.argtypes = [vp, vp, vp, vp, vp]
@@ -145,6 +149,13 @@ def reference_operators(P: int):
     return dict(Dr=Dr, Ds=Ds, LIFT=LIFT, Vinv=Vinv)
 
 
+def prolong_operator(P: int, Q: int):
+    """(Np(Q), Np(P)) prolongation matrix of the library (p-refinement)."""
+    I = np.zeros((n_nodes(Q), n_nodes(P)))
+    _check(lib().dg_prolong_operator(int(P), int(Q), _p(I)))
+    return I
+
+
 def _stream_handle(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -171,7 +182,7 @@ class Solver:
 
     def __init__(self, EToE, EToF, bc, x, y, P, precision="fp32", gamma=1.4, cfl=0.5,
                  freestream=(1.0, 0.0, 0.0, 2.5), av=False, av_eps0=0.3, av_s0=float("nan"),
-                 av_kappa=1.0, device="cuda:0"):
+                 av_kappa=1.0, riemann="lf", device="cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -198,6 +209,9 @@ class Solver:
         d.av_eps0 = av_eps0
         d.av_s0 = av_s0 if av_s0 is not None else float("nan")
         d.av_kappa = av_kappa
+        if riemann not in RIEMANN:
+            raise ValueError(f"riemann must be one of {sorted(RIEMANN)}")
+        d.riemann = RIEMANN[riemann]
         self.av = bool(av)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -259,6 +273,15 @@ class Solver:
         _check(lib().dg_step(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
                              float(dt), _stream_handle(stream)))
         return U
+
+    def prolong_from(self, other, U_other, stream=None):
+        """This solver's state (order Q) prolonged from the state of `other`
+        (same elements, order P <= Q)."""
+        other._check_state(U_other)
+        out = self.empty_state()
+        _check(lib().dg_prolong(other._h, C.c_void_p(U_other.data_ptr()), self._h, C.c_void_p(out.data_ptr()),
+                                _stream_handle(stream)))
+        return out
 
     def run(self, U, nsteps, stream=None, check=True):
         self._check_state(U)

@@ -43,6 +43,7 @@ class Request:
     finished: float = math.nan
     status: int = 0
     t_sim: float = math.nan
+    steps_run: int = 0           # steps the solve actually ran (fewer if it stopped)
     final_state: object = None   # host copy of the result when the server keeps states
     error: str = ""
 
@@ -109,15 +110,22 @@ class Report:
     extra: dict = field(default_factory=dict)
 
     def summary(self):
+        """Latency percentiles over every request (one that stopped on the
+        state check or failed its setup counts at the time it stopped:
+        censored, not dropped) and over the completed ones; throughput from
+        the steps every request actually ran."""
         done = [r for r in self.requests if r.status == 0]
+        lat_all = np.array([r.latency for r in self.requests])
         lat = np.array([r.latency for r in done]) if done else np.array([math.nan])
-        total = sum(r.dofs * 5 * r.steps for r in done)
+        total = sum(r.dofs * 5 * r.steps_run for r in self.requests)
         first = min(r.arrival for r in self.requests)
         last = max(r.finished for r in self.requests)
         return dict(n_requests=len(self.requests), precision=self.precision,
-                    p50_latency_s=float(np.percentile(lat, 50)),
-                    p99_latency_s=float(np.percentile(lat, 99)),
-                    mean_latency_s=float(lat.mean()),
+                    p50_latency_s=float(np.percentile(lat_all, 50)),
+                    p99_latency_s=float(np.percentile(lat_all, 99)),
+                    p50_latency_completed_s=float(np.percentile(lat, 50)),
+                    p99_latency_completed_s=float(np.percentile(lat, 99)),
+                    mean_latency_s=float(lat_all.mean()),
                     dof_updates=float(total),
                     aggregate_dof_updates_per_s=float(total / (last - first)),
                     makespan_s=float(last - first), peak_slots=self.peak_slots,
@@ -201,6 +209,7 @@ class Server:
                 req.finished = time.perf_counter() - t0
                 req.status = st.status
                 req.t_sim = st.t
+                req.steps_run = st.steps
                 if self.keep_states:
                     req.final_state = U.double().cpu().numpy()
                 batch.release(slot)
@@ -222,7 +231,7 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--mean-gap", type=float, default=0.05)
     ap.add_argument("--seed", type=int, default=64)
-    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--budget-gib", type=float, default=1.0)
     ap.add_argument("--max-slots", type=int, default=16)
     ap.add_argument("--chunk-steps", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
