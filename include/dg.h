@@ -168,6 +168,22 @@ int dg_rhs(dg_mesh *mesh, const void *U, void *rhs, double t, void *stream);
  * of dg_buffer_bytes' work_bytes.  Enqueues only (no host round trip). */
 int dg_step(dg_mesh *mesh, void *U, void *work, double dt, void *stream);
 
+/* Size of the static work area of dg_step_static (256 MiB). */
+#define DG_STATIC_WORK_BYTES (256u << 20)
+
+/* dg_step without a work argument, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid
+ * allocation): the work buffer is a file-scope device array of
+ * DG_STATIC_WORK_BYTES that every GPU the library runs on holds until the
+ * process ends.  The call allocates nothing.  Meshes whose work_bytes
+ * (dg_buffer_bytes) exceed DG_STATIC_WORK_BYTES get DG_EINVAL.  Nothing in
+ * the area needs to start at zero: a step writes the Runge-Kutta register
+ * and the stage buffers before it reads them.  All calls on one GPU share
+ * the area: calls that overlap on one GPU (different streams, or different
+ * handles at once) race.  Same results as dg_step with a caller work buffer.
+ * Enqueues only. */
+int dg_step_static(dg_mesh *mesh, void *U, double dt, void *stream);
+
 /* nsteps CFL steps of U in place, then totals and residual; synchronises
  * and fills *stats (may be NULL).  Returns DG_ENONFINITE if the state
  * became non-finite, rho <= 0 or p <= 0 at any step.  FP32 handles take

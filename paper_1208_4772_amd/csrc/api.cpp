@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -545,6 +546,51 @@ static int ensure_step_graph(dg_mesh *m, void *U, void *work) {
     if (ei != hipSuccess) return fail(DG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     m->graph_U = U;
     m->graph_work = work;
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step without a caller work buffer: the work lives in a file-scope device
+// array of fixed size (one copy per GPU, held until the process ends)
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[DG_STATIC_WORK_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device, with that device current).  The array's name is only a host-side
+// stand-in; every use from the host goes through this address.
+int scratch_address(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DG_EDEVICE, "device id out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(DG_EDEVICE, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DG_OK;
+}
+}  // namespace
+
+int dg_step_static(dg_mesh *m, void *U, double dt, void *stream) {
+    if (!m) return fail(DG_EINVAL, "mesh is NULL");
+    if (int rc = check_ptr(U, "U")) return rc;
+    if (m->work_bytes() > size_t(DG_STATIC_WORK_BYTES))
+        return fail(DG_EINVAL, "work buffer of " + std::to_string(m->work_bytes()) + " bytes exceeds the " +
+                                   std::to_string(size_t(DG_STATIC_WORK_BYTES)) + "-byte static work area");
+    void *work = nullptr;
+    if (int rc = scratch_address(&work)) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (int rc = step_impl(m, U, work, dt, st)) return rc;
+    m->mark(st);
     return DG_OK;
 }
 

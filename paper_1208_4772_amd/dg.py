@@ -32,7 +32,7 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_autotune", "dg_mesh_footprint",
            "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
-           "dg_status", "dg_prolong_operator", "dg_prolong")
+           "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong")
 
 
 class DGError(RuntimeError):
@@ -83,6 +83,7 @@ def lib():
         L.dg_buffer_bytes.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.dg_rhs.argtypes = [vp, vp, vp, d, vp]
         L.dg_step.argtypes = [vp, vp, vp, d, vp]
+        L.dg_step_static.argtypes = [vp, vp, d, vp]
         L.dg_prolong_operator.argtypes = [i, i, vp]
         L.dg_prolong.argtypes = [vp, vp, vp, vp, vp]
         L.dg_run.argtypes = [vp, vp, vp, i, C.POINTER(RunStats), vp]
@@ -272,6 +273,13 @@ class Solver:
         self._check_state(U)
         _check(lib().dg_step(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
                              float(dt), _stream_handle(stream)))
+        return U
+
+    def step_static(self, U, dt=0.0, stream=None):
+        """One step with the library's static work area instead of this
+        solver's work buffer (dg_step_static)."""
+        self._check_state(U)
+        _check(lib().dg_step_static(self._h, C.c_void_p(U.data_ptr()), float(dt), _stream_handle(stream)))
         return U
 
     def prolong_from(self, other, U_other, stream=None):
