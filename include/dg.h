@@ -81,6 +81,17 @@ enum dg_bc { DG_BC_INTERIOR = 0, DG_BC_WALL = 1, DG_BC_FARFIELD = 2 };
  * Speares, evaluated in the frame of the face normal. */
 enum dg_riemann { DG_RIEMANN_LF = 0, DG_RIEMANN_HLLC = 1 };
 
+/* Discretisation of the volume and surface terms.  DG_FORM_NODAL: the
+ * nodal strong form (fluxes collocated at the nodes, Dr/Ds and LIFT).
+ * DG_FORM_WEAK: the paper's over-integrated weak form (Section 2, eqs.
+ * stiffness, mass, face_mass, semidiscrete): the state interpolated to a
+ * collapsed Gauss product rule of n x n points exact for degree 3P
+ * (n = (3P+2)/2) and to n Gauss points per face, M_k dU/dt = V - S with the
+ * per-element mass matrix (inverted by Cholesky for curved elements at
+ * setup).  Inviscid only (av_enable must be 0); FP64 or FP32 state, VALU
+ * contractions; time step as for the nodal form. */
+enum dg_form { DG_FORM_NODAL = 0, DG_FORM_WEAK = 1 };
+
 /* Message of the last error on this thread ("" if none). */
 const char *dg_last_error(void);
 
@@ -104,6 +115,15 @@ int dg_face_nodes(int P, int *fmask);
  * orthonormal modal coefficients, f = V f_hat).  Any pointer may be NULL. */
 int dg_reference_operators(int P, double *Dr, double *Ds, double *LIFT, double *Vinv);
 
+/* Operators of the weak form of order P as built by the library (host,
+ * FP64): *ncub cubature points and *ng Gauss points per face; wq [ncub]
+ * weights, Icub, Drc, Dsc [ncub*Np] (nodal basis and its r, s derivatives
+ * at the cubature points, row-major), wg [ng] face weights, If [ng*Nfp]
+ * (the face nodes' 1D Lagrange basis at the face Gauss points).  Call with
+ * NULL arrays to learn the sizes; any pointer may be NULL. */
+int dg_weak_operators(int P, int *ncub, int *ng, double *wq, double *Icub, double *Drc, double *Dsc,
+                      double *wg, double *If);
+
 typedef struct {
     int K;                        /* elements, >= 1 */
     int P;                        /* order, 1..5 */
@@ -120,6 +140,7 @@ typedef struct {
     double av_s0;                 /* ramp centre; NaN: -4 log10 P */
     double av_kappa;              /* ramp half-width, > 0 */
     int riemann;                  /* enum dg_riemann */
+    int form;                     /* enum dg_form */
 } dg_mesh_desc;
 
 typedef struct dg_mesh dg_mesh;   /* opaque handle */
@@ -269,7 +290,7 @@ int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *by
  * that kind (viscous slots add one sensor and one gradient launch per
  * stage over all of them), each with its own CFL time step computed on the
  * device; FP64 slots are stepped one by one in the same stream.  Two steps are captured in a hipGraph and replayed
- * while the membership does not change.  The result of every slot is
+ * (see dg_batch_info for when it is captured again).  The result of every slot is
  * bit-identical to running it alone with dg_run.  Slots join (admit) and
  * leave (release) between calls, so solves that arrive while others are
  * running start at the next call. */
@@ -300,6 +321,15 @@ int dg_batch_poll(dg_batch *batch, void *stream, int *done_slots, int max_done, 
 
 /* Steps done, simulated time, dt range and status of a slot (synchronises). */
 int dg_batch_slot_stats(dg_batch *batch, int slot, void *stream, dg_run_stats *stats);
+
+/* Step graphs the batch has captured so far, and the kinds of solve (order,
+ * product precision, viscosity) it holds tables for.  The batched launches
+ * read their work lists' lengths from device memory and a kind's tables
+ * stay once created, so the captured two-step graph stays valid while
+ * solves join and leave; it is captured again only when a new kind
+ * appears, a work list outgrows its table or the set of FP64 slots (stepped
+ * one by one inside the graph) changes. */
+int dg_batch_info(dg_batch *batch, int *captures, int *groups);
 
 /* Free a slot and its share of the budget; the handle and buffers stay the
  * caller's. */

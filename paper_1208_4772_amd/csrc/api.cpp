@@ -173,6 +173,24 @@ int dg_reference_operators(int P, double *Dr, double *Ds, double *LIFT, double *
     return DG_OK;
 }
 
+int dg_weak_operators(int P, int *ncub, int *ng, double *wq, double *Icub, double *Drc, double *Dsc, double *wg,
+                      double *If) {
+    WeakOps W;
+    if (P < 1 || P > 5 || !build_weak(P, W)) return fail(DG_EINVAL, "order P must be 1..5");
+    if (ncub) *ncub = W.ncub;
+    if (ng) *ng = W.ng;
+    auto put = [](double *dst, const std::vector<double> &v) {
+        if (dst) std::memcpy(dst, v.data(), sizeof(double) * v.size());
+    };
+    put(wq, W.wq);
+    put(Icub, W.Icub);
+    put(Drc, W.Drc);
+    put(Dsc, W.Dsc);
+    put(wg, W.wg);
+    put(If, W.If);
+    return DG_OK;
+}
+
 int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     if (!out) return fail(DG_EINVAL, "out is NULL");
     *out = nullptr;
@@ -188,6 +206,12 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         return fail(DG_EINVAL, "av_kappa must be > 0 and av_eps0 >= 0");
     if (d->riemann != DG_RIEMANN_LF && d->riemann != DG_RIEMANN_HLLC)
         return fail(DG_EINVAL, "riemann must be DG_RIEMANN_LF or DG_RIEMANN_HLLC");
+    if (d->form != DG_FORM_NODAL && d->form != DG_FORM_WEAK)
+        return fail(DG_EINVAL, "form must be DG_FORM_NODAL or DG_FORM_WEAK");
+    if (d->form == DG_FORM_WEAK && d->av_enable)
+        return fail(DG_EINVAL, "the weak form is inviscid: av_enable must be 0");
+    if (d->form == DG_FORM_WEAK && d->precision == DG_FP32_BF16X3)
+        return fail(DG_EINVAL, "the weak form runs in DG_FP64_PLAIN or DG_FP32");
     const int K = d->K, P = d->P;
     RefOps ref;
     if (!build_reference(P, ref)) return fail(DG_EINVAL, "reference element construction failed");
@@ -237,6 +261,7 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     dm.bf3 = d->precision == DG_FP32_BF16X3;
     dm.av = d->av_enable != 0;
     dm.riemann = d->riemann;
+    dm.weak = d->form == DG_FORM_WEAK;
     dm.gamma = d->gamma;
     dm.cfl = d->cfl;
     for (int c = 0; c < 4; ++c) dm.qinf[c] = d->freestream[c];
@@ -388,6 +413,88 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         if (const char *e = std::getenv("DG_WAVES_PER_BLOCK")) {
             const int w = std::atoi(e);
             if (w == 2 || w == 4 || w == 8) dm.waves_per_block = w;
+        }
+        SETUP_TRY(hipStreamSynchronize(st));
+    }
+    if (dm.weak) {
+        // over-integrated weak form: cubature operators and the per-element
+        // tables, computed in FP64 on the device; curved elements are those
+        // whose nodal metric terms are not constant
+        WeakOps W;
+        if (!build_weak(P, W)) {
+            fail(DG_EINVAL, "weak-form operator construction failed");
+            return cleanup(DG_EINVAL);
+        }
+        const int NQ = W.ncub, NG = W.ng;
+        std::vector<double> wops;
+        wops.insert(wops.end(), W.Icub.begin(), W.Icub.end());
+        wops.insert(wops.end(), W.Drc.begin(), W.Drc.end());
+        wops.insert(wops.end(), W.Dsc.begin(), W.Dsc.end());
+        wops.insert(wops.end(), W.wq.begin(), W.wq.end());
+        wops.insert(wops.end(), W.If.begin(), W.If.end());
+        wops.insert(wops.end(), W.Minv.begin(), W.Minv.end());
+        if (wops.size() != weak_ops_size(P)) {
+            fail(DG_EINVAL, "internal: weak-form operator table size");
+            return cleanup(DG_EINVAL);
+        }
+        std::vector<double> dsg;
+        dsg.insert(dsg.end(), W.Drg.begin(), W.Drg.end());
+        dsg.insert(dsg.end(), W.Dsg.begin(), W.Dsg.end());
+        dsg.insert(dsg.end(), W.wg.begin(), W.wg.end());
+        double *wops_d, *dsg_d, *geoA_d, *geoF_d;
+        int *wflags_d, *widx_d;
+        if ((rc = m->alloc(&wops_d, wops.size())) || (rc = m->alloc(&dsg_d, dsg.size())) ||
+            (rc = m->alloc(&geoA_d, size_t(K) * 5)) || (rc = m->alloc(&geoF_d, size_t(K) * 3 * NG * 3)) ||
+            (rc = m->alloc(&wflags_d, size_t(K))) || (rc = m->alloc(&widx_d, size_t(K))))
+            return cleanup(rc);
+        SETUP_TRY(hipMemcpyAsync(wops_d, wops.data(), sizeof(double) * wops.size(), hipMemcpyHostToDevice, st));
+        SETUP_TRY(hipMemcpyAsync(dsg_d, dsg.data(), sizeof(double) * dsg.size(), hipMemcpyHostToDevice, st));
+        dm.wops64 = wops_d;
+        SETUP_TRY(launch_affine_flags(dm, wflags_d, st));
+        std::vector<int> wflags(K), widx(K);
+        SETUP_TRY(hipMemcpyAsync(wflags.data(), wflags_d, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+        SETUP_TRY(hipStreamSynchronize(st));
+        int Kc = 0;
+        for (long k = 0; k < K; ++k) widx[k] = wflags[k] ? -1 : Kc++;
+        SETUP_TRY(hipMemcpyAsync(widx_d, widx.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+        dm.widx = widx_d;
+        dm.wKc = Kc;
+        double *geoC_d, *minv_d, *work_d;
+        if ((rc = m->alloc(&geoC_d, size_t(Kc) * NQ * 4 + 1)) || (rc = m->alloc(&minv_d, size_t(Kc) * Np * Np + 1)) ||
+            (rc = m->alloc(&work_d, size_t(Kc) * Np * Np + 1)))
+            return cleanup(rc);
+        SETUP_TRY(hipMemsetAsync(count_d, 0, sizeof(int) * 4, st));
+        SETUP_TRY(launch_weak_geometry(dm, x_d, y_d, dsg_d, dsg_d + W.Drg.size(), dsg_d + 2 * W.Drg.size(), geoA_d,
+                                       geoF_d, geoC_d, minv_d, work_d, st));
+        int wc[4] = {0, 0, 0, 0};
+        SETUP_TRY(hipMemcpyAsync(wc, count_d, sizeof(wc), hipMemcpyDeviceToHost, st));
+        SETUP_TRY(hipStreamSynchronize(st));
+        if (wc[0] > 0 || wc[2] > 0) {
+            fail(DG_EGEOM, std::to_string(wc[0]) + " cubature points with J <= 0, " + std::to_string(wc[2]) +
+                               " mass matrices not positive definite");
+            return cleanup(DG_EGEOM);
+        }
+        dm.wgeoA64 = geoA_d;
+        dm.wgeoF64 = geoF_d;
+        dm.wgeoC64 = geoC_d;
+        dm.wminv64 = minv_d;
+        if (dm.fp32) {
+            float *o32, *a32, *f32, *c32, *m32;
+            const size_t nC = size_t(Kc) * NQ * 4, nM = size_t(Kc) * Np * Np;
+            if ((rc = m->alloc(&o32, wops.size())) || (rc = m->alloc(&a32, size_t(K) * 5)) ||
+                (rc = m->alloc(&f32, size_t(K) * 3 * NG * 3)) || (rc = m->alloc(&c32, nC + 1)) ||
+                (rc = m->alloc(&m32, nM + 1)))
+                return cleanup(rc);
+            SETUP_TRY(launch_cast(wops_d, o32, wops.size(), st));
+            SETUP_TRY(launch_cast(geoA_d, a32, size_t(K) * 5, st));
+            SETUP_TRY(launch_cast(geoF_d, f32, size_t(K) * 3 * NG * 3, st));
+            SETUP_TRY(launch_cast(geoC_d, c32, nC, st));
+            SETUP_TRY(launch_cast(minv_d, m32, nM, st));
+            dm.wops32 = o32;
+            dm.wgeoA32 = a32;
+            dm.wgeoF32 = f32;
+            dm.wgeoC32 = c32;
+            dm.wminv32 = m32;
         }
         SETUP_TRY(hipStreamSynchronize(st));
     }
@@ -653,7 +760,7 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
     HIP_TRY(launch_reset_scalars(m->dm, st));
     HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
     HIP_TRY(hipEventRecord(e0, st));
-    const bool fused = m->dm.fp32;
+    const bool fused = m->dm.fp32 && !m->dm.weak;
     if (fused && nsteps > 0) {
         if (m->dm.av)
             HIP_TRY(hipMemsetAsync(m->dm.vmax, 0, 2 * kVmaxSlots * sizeof(unsigned long long), st));
@@ -774,7 +881,7 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
     if (int rc = check_ptr(work, "work")) return rc;
     if (waves_per_block) *waves_per_block = 0;
     if (stage_us) *stage_us = 0.0;
-    if (!m->dm.fp32 || m->dm.av) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
+    if (!m->dm.fp32 || m->dm.av || m->dm.weak) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
     hipStream_t st = static_cast<hipStream_t>(stream);
     // candidates: workgroups of 2, 4 and 8 wavefronts (2, 4 or 8 times the
     // elements one wavefront holds), each timed over the five Runge-Kutta
@@ -908,21 +1015,25 @@ struct Slot {
 
 // Device tables of one order P: argument records [parity][stage][job] and
 // the work list of (job, tile) items.
+// Device tables of one kind of solve (order P, BF16x3 product, viscosity):
+// argument records [parity][stage][job] (job stride: the batch's slot
+// count) and the work lists of (job, tile) items, with their lengths in
+// device memory.  A group, once it has appeared, stays until the batch is
+// destroyed (an empty group's launches find an empty list), so a captured
+// step stays valid while solves of known kinds join and leave.
 struct Group {
     int P = 0;
     bool bf3 = false;
     bool av = false;               // viscous handles: sensor and gradient records too
     std::vector<int> slots;
-    void *jobs = nullptr;
-    size_t jobs_cap = 0;
-    void *avjobs = nullptr;        // [parity][stage][job] sensor/gradient records
-    size_t avjobs_cap = 0;
+    void *jobs = nullptr;          // [2][5][max_slots] stage records
+    void *avjobs = nullptr;        // [2][5][max_slots] sensor/gradient records
     void *items = nullptr;
-    size_t items_cap = 0;
-    int nitems = 0;
+    size_t items_cap = 0;          // entries (int2)
     void *eitems = nullptr;        // viscous: (job, block of 256 elements) for the per-element sensor
     size_t eitems_cap = 0;
-    int neitems = 0;
+    int *counts = nullptr;         // device [2]: items, eitems
+    int nitems = 0, neitems = 0;
 };
 
 }  // namespace
@@ -932,11 +1043,13 @@ struct dg_batch {
     std::vector<Slot> slots;
     std::vector<Group> groups;
     std::vector<int> singles;      // slots stepped one by one (FP64 handles)
+    std::vector<int> prev_singles; // the set the captured graph holds
     bool dirty = true;
     long epoch_steps = 0;          // steps since the tables were last built
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     hipEvent_t done = nullptr;     // end of the last advance's work; destroy waits for it
+    int captures = 0;              // step graphs captured so far
     ~dg_batch() {
         if (done) (void)hipEventDestroy(done);
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -946,53 +1059,62 @@ struct dg_batch {
             if (g.avjobs) (void)hipFree(g.avjobs);
             if (g.items) (void)hipFree(g.items);
             if (g.eitems) (void)hipFree(g.eitems);
+            if (g.counts) (void)hipFree(g.counts);
         }
     }
 };
 
 namespace {
 
-bool batched_path(const dg_mesh *m) { return m->dm.fp32; }
+bool batched_path(const dg_mesh *m) { return m->dm.fp32 && !m->dm.weak; }
 
-// Rebuild the per-order tables for the active, unfinished slots.
+// Rebuild the per-kind tables for the active, unfinished slots.  Groups are
+// kept once created; the step graph is captured again only when a new group
+// appears or a work list outgrows its table.
 int rebuild(dg_batch *b, hipStream_t st) {
-    std::vector<Group> old;
-    old.swap(b->groups);
     b->singles.clear();
+    const size_t max_jobs = b->slots.size();
+    bool stale_graph = false;
     for (int key = 0; key < 20; ++key) {
-        Group g;
-        g.P = 1 + key % 5;
-        g.bf3 = (key / 5) & 1;
-        g.av = key >= 10;
+        const int P = 1 + key % 5;
+        const bool bf3 = (key / 5) & 1, av = key >= 10;
+        std::vector<int> members;
         for (size_t i = 0; i < b->slots.size(); ++i) {
             const Slot &s = b->slots[i];
-            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == g.P &&
-                s.mesh->dm.bf3 == g.bf3 && s.mesh->dm.av == g.av)
-                g.slots.push_back(int(i));
+            if (s.used && !s.finished && batched_path(s.mesh) && s.mesh->dm.P == P && s.mesh->dm.bf3 == bf3 &&
+                s.mesh->dm.av == av)
+                members.push_back(int(i));
         }
-        if (!g.slots.empty()) b->groups.push_back(std::move(g));
+        Group *g = nullptr;
+        for (Group &o : b->groups)
+            if (o.P == P && o.bf3 == bf3 && o.av == av) g = &o;
+        if (!g) {
+            if (members.empty()) continue;
+            Group ng;
+            ng.P = P;
+            ng.bf3 = bf3;
+            ng.av = av;
+            if (hipMalloc(&ng.jobs, 2 * 5 * max_jobs * mfma_args_bytes()) != hipSuccess ||
+                (av && hipMalloc(&ng.avjobs, 2 * 5 * max_jobs * av_args_bytes()) != hipSuccess) ||
+                hipMalloc(reinterpret_cast<void **>(&ng.counts), 2 * sizeof(int)) != hipSuccess) {
+                if (ng.jobs) (void)hipFree(ng.jobs);
+                if (ng.avjobs) (void)hipFree(ng.avjobs);
+                return fail(DG_ENOMEM, "batch table allocation failed");
+            }
+            b->groups.push_back(ng);
+            g = &b->groups.back();
+            stale_graph = true;
+        }
+        g->slots = members;
     }
     for (size_t i = 0; i < b->slots.size(); ++i) {
         const Slot &s = b->slots[i];
         if (s.used && !s.finished && !batched_path(s.mesh)) b->singles.push_back(int(i));
     }
-    // reuse old allocations where they are large enough
     for (Group &g : b->groups) {
-        for (Group &o : old)
-            if (o.P == g.P && o.bf3 == g.bf3 && o.av == g.av) {
-                g.jobs = o.jobs;
-                g.jobs_cap = o.jobs_cap;
-                g.avjobs = o.avjobs;
-                g.avjobs_cap = o.avjobs_cap;
-                g.items = o.items;
-                g.items_cap = o.items_cap;
-                g.eitems = o.eitems;
-                g.eitems_cap = o.eitems_cap;
-                o.jobs = o.avjobs = o.items = o.eitems = nullptr;
-            }
         const size_t nj = g.slots.size();
         const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
-        std::vector<char> jobs(2 * 5 * nj * rec), avjobs(g.av ? 2 * 5 * nj * arec : 0);
+        std::vector<char> jobs(2 * 5 * max_jobs * rec, 0), avjobs(g.av ? 2 * 5 * max_jobs * arec : 0, 0);
         std::vector<int> items, eitems;
         for (size_t j = 0; j < nj; ++j) {
             Slot &s = b->slots[g.slots[j]];
@@ -1020,10 +1142,10 @@ int rebuild(dg_batch *b, hipStream_t st) {
                         ms.vmax_out = vout;
                     }
                     mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms,
-                                   jobs.data() + ((ps * 5 + st5) * nj + j) * rec, eps, Q);
+                                   jobs.data() + ((ps * 5 + st5) * max_jobs + j) * rec, eps, Q);
                     if (g.av)
                         av_fill_args(m->dm, in[st5], eps, Q, st5 == 0 ? vin : nullptr,
-                                     avjobs.data() + ((ps * 5 + st5) * nj + j) * arec);
+                                     avjobs.data() + ((ps * 5 + st5) * max_jobs + j) * arec);
                 }
             }
             const int nt = mfma_tiles(m->dm);
@@ -1041,37 +1163,45 @@ int rebuild(dg_batch *b, hipStream_t st) {
         }
         g.nitems = int(items.size() / 2);
         g.neitems = int(eitems.size() / 2);
+        // work lists grow by doubling; a new table means a new address, so
+        // the captured graph is stale
         auto grow = [&](void **p, size_t *cap, size_t need) -> int {
-            if (*cap >= need) return DG_OK;
+            if (*cap >= need && *p) return DG_OK;
+            size_t nc = *cap ? *cap : 4096;
+            while (nc < need) nc *= 2;
             if (*p) (void)hipFree(*p);
             *p = nullptr;
             *cap = 0;
-            if (hipMalloc(p, need) != hipSuccess) return fail(DG_ENOMEM, "batch table allocation failed");
-            *cap = need;
+            if (hipMalloc(p, nc * 2 * sizeof(int)) != hipSuccess) return fail(DG_ENOMEM, "batch table allocation failed");
+            *cap = nc;
+            stale_graph = true;
             return DG_OK;
         };
-        if (int rc = grow(&g.jobs, &g.jobs_cap, jobs.size())) return rc;
-        if (int rc = grow(&g.items, &g.items_cap, items.size() * sizeof(int))) return rc;
+        if (int rc = grow(&g.items, &g.items_cap, size_t(g.nitems))) return rc;
+        if (g.av)
+            if (int rc = grow(&g.eitems, &g.eitems_cap, size_t(g.neitems))) return rc;
         HIP_TRY(hipMemcpyAsync(g.jobs, jobs.data(), jobs.size(), hipMemcpyHostToDevice, st));
-        if (g.av) {
-            if (int rc = grow(&g.avjobs, &g.avjobs_cap, avjobs.size())) return rc;
-            HIP_TRY(hipMemcpyAsync(g.avjobs, avjobs.data(), avjobs.size(), hipMemcpyHostToDevice, st));
-            if (int rc = grow(&g.eitems, &g.eitems_cap, eitems.size() * sizeof(int))) return rc;
-            HIP_TRY(hipMemcpyAsync(g.eitems, eitems.data(), eitems.size() * sizeof(int), hipMemcpyHostToDevice,
-                                   st));
-        }
-        HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if (g.av) HIP_TRY(hipMemcpyAsync(g.avjobs, avjobs.data(), avjobs.size(), hipMemcpyHostToDevice, st));
+        if (!items.empty())
+            HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if (!eitems.empty())
+            HIP_TRY(hipMemcpyAsync(g.eitems, eitems.data(), eitems.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        const int counts[2] = {g.nitems, g.neitems};
+        HIP_TRY(hipMemcpyAsync(g.counts, counts, sizeof(counts), hipMemcpyHostToDevice, st));
+        // the host buffers go out of scope: wait for the copies
+        HIP_TRY(hipStreamSynchronize(st));
     }
-    for (Group &o : old) {
-        if (o.jobs) (void)hipFree(o.jobs);
-        if (o.avjobs) (void)hipFree(o.avjobs);
-        if (o.items) (void)hipFree(o.items);
-        if (o.eitems) (void)hipFree(o.eitems);
-    }
-    if (b->graph) {
+    if (stale_graph && b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    // FP64 slots step inside the graph too, their launches carrying their
+    // buffers: a change of that set needs a new graph
+    if (b->singles != b->prev_singles && b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->prev_singles = b->singles;
     b->epoch_steps = 0;
     b->dirty = false;
     return DG_OK;
@@ -1079,15 +1209,15 @@ int rebuild(dg_batch *b, hipStream_t st) {
 
 // One lockstep step of every active slot; ps = parity of the epoch step.
 int batch_step(dg_batch *b, int ps, hipStream_t st) {
-    const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
+    const size_t rec = mfma_args_bytes(), arec = av_args_bytes(), nj = b->slots.size();
     for (int s5 = 0; s5 < 5; ++s5)
         for (const Group &g : b->groups) {
             if (g.av) {
-                const char *avjobs = static_cast<const char *>(g.avjobs) + (ps * 5 + s5) * g.slots.size() * arec;
-                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.nitems, g.eitems, g.neitems, st));
+                const char *avjobs = static_cast<const char *>(g.avjobs) + (ps * 5 + s5) * nj * arec;
+                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.counts, g.eitems, g.counts + 1, st));
             }
-            const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * g.slots.size() * rec;
-            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, jobs, g.items, g.nitems, st));
+            const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * nj * rec;
+            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, jobs, g.items, g.counts, st));
         }
     for (int i : b->singles) {
         Slot &s = b->slots[i];
@@ -1200,6 +1330,7 @@ int dg_batch_advance(dg_batch *b, int max_steps, void *stream, int *steps_run) {
             hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (ei != hipSuccess) return fail(DG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+            ++b->captures;
         }
         for (; done + 2 <= n; done += 2) {
             HIP_TRY(hipGraphLaunch(b->graph, st));
@@ -1275,6 +1406,13 @@ int dg_batch_slot_stats(dg_batch *b, int slot, void *stream, dg_run_stats *stats
     stats->t = scal[S_T];
     stats->dt_min = stats->steps ? scal[S_DTMIN] : 0.0;
     stats->dt_max = scal[S_DTMAX];
+    return DG_OK;
+}
+
+int dg_batch_info(dg_batch *b, int *captures, int *groups) {
+    if (!b) return fail(DG_EINVAL, "batch is NULL");
+    if (captures) *captures = b->captures;
+    if (groups) *groups = int(b->groups.size());
     return DG_OK;
 }
 

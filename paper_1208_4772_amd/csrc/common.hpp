@@ -244,8 +244,21 @@ __device__ inline void flux_jump(int riemann, T g, const T um[kFields], const T 
 // viscous term; reading R11), always in FP64 whatever the state precision:
 // 1/2 (P+1)^2 Fscale (|v| + c) + 1/4 (P+1)^4 Fscale^2 eps.
 __device__ inline double cfl_bound(double g, const double u[kFields], double fs, double e, double P1) {
-    const double vx = u[1] / u[0], vy = u[2] / u[0];
-    const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * pressure(g, u) / u[0]);
+    const double ir = 1.0 / u[0];
+    const double vx = u[1] * ir, vy = u[2] * ir;
+    const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * pressure_ir(g, u, ir) * ir);
+    return 0.5 * P1 * P1 * fs * lam + 0.25 * P1 * P1 * P1 * P1 * fs * fs * e;
+}
+
+// The same bound for a node that also takes the state check (one division).
+__device__ inline double cfl_bound_checked(double g, const double u[kFields], double fs, double e, double P1,
+                                           int &bad) {
+    const double ir = 1.0 / u[0];
+    const double vx = u[1] * ir, vy = u[2] * ir;
+    const double p = pressure_ir(g, u, ir);
+    if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) || !isfinite(p))
+        bad = 1;
+    const double lam = sqrt(vx * vx + vy * vy) + sqrt(g * p * ir);
     return 0.5 * P1 * P1 * fs * lam + 0.25 * P1 * P1 * P1 * P1 * fs * fs * e;
 }
 

@@ -511,29 +511,43 @@ __global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
 
 // Batched meshes of one order (FP32 viscous handles): work item = (job,
 // tile), a job being one mesh's argument record for this stage.
+// All three are persistent over their work list, whose length they read
+// from device memory (a captured launch stays valid when the list changes).
 template <int P, bool CFL>
 __global__ __launch_bounds__(kBlock) void k_sensor_batch(const AvArgs<float> *__restrict__ jobs,
-                                                         const int2 *__restrict__ items, int nitems) {
-    if ((int)blockIdx.x >= nitems) return;
-    const int2 it = items[blockIdx.x];
-    sensor_body<float, P, CFL>(jobs[it.x], it.y);
+                                                         const int2 *__restrict__ items,
+                                                         const int *__restrict__ nitems_dev) {
+    const int n = *nitems_dev;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        sensor_body<float, P, CFL>(jobs[it.x], it.y);
+        __syncthreads();
+    }
 }
 
 // Batched per-element sensor: work item = (job, block of kBlock elements).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_sensor_elem_batch(const AvArgs<float> *__restrict__ jobs,
-                                                              const int2 *__restrict__ items, int nitems) {
-    if ((int)blockIdx.x >= nitems) return;
-    const int2 it = items[blockIdx.x];
-    sensor_elem_body<float, P>(jobs[it.x], it.y);
+                                                              const int2 *__restrict__ items,
+                                                              const int *__restrict__ nitems_dev) {
+    const int n = *nitems_dev;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        sensor_elem_body<float, P>(jobs[it.x], it.y);
+        __syncthreads();
+    }
 }
 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_avgrad_batch(const AvArgs<float> *__restrict__ jobs,
-                                                         const int2 *__restrict__ items, int nitems) {
-    if ((int)blockIdx.x >= nitems) return;
-    const int2 it = items[blockIdx.x];
-    avgrad_body<float, P>(jobs[it.x], it.y);
+                                                         const int2 *__restrict__ items,
+                                                         const int *__restrict__ nitems_dev) {
+    const int n = *nitems_dev;
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const int2 it = items[w];
+        avgrad_body<float, P>(jobs[it.x], it.y);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,7 +1035,9 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) 
 
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                         const void *eps, const void *Q, hipStream_t st) {
-    // FP32 (with or without viscosity): the matrix-core kernel; FP64: VALU
+    // the weak form: its own kernel; FP32 (with or without viscosity): the
+    // matrix-core kernel; FP64: VALU
+    if (m.weak) return launch_stage_weak(m, Uin, Uout, R, rhs, stage, st);
     if (m.fp32) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st, eps, Q);
     return stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }
@@ -1068,21 +1084,23 @@ void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned 
 
 int sensor_elem_blocks(const DevMesh &m) { return (m.K + kBlock - 1) / kBlock; }
 
-hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems,
-                           const void *eitems, int neitems, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, const int *nitems_dev,
+                           const void *eitems, const int *neitems_dev, hipStream_t st) {
     const auto *j = static_cast<const AvArgs<float> *>(jobs);
     const auto *it = static_cast<const int2 *>(items);
     const auto *eit = static_cast<const int2 *>(eitems);
     return with_order(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
+        static const int gs = resident_grid(k_sensor_batch<PP, true>, kBlock);
+        static const int ge = resident_grid(k_sensor_elem_batch<PP>, kBlock);
+        static const int gg = resident_grid(k_avgrad_batch<PP>, kBlock);
         if (cfl)
-            hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
-        else if (neitems > 0)
-            hipLaunchKernelGGL((k_sensor_elem_batch<PP>), dim3(neitems), dim3(kBlock), 0, st, j, eit, neitems);
+            hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(gs), dim3(kBlock), 0, st, j, it, nitems_dev);
+        else
+            hipLaunchKernelGGL((k_sensor_elem_batch<PP>), dim3(ge), dim3(kBlock), 0, st, j, eit, neitems_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(nitems), dim3(kBlock), 0, st, j, it, nitems);
+        hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(gg), dim3(kBlock), 0, st, j, it, nitems_dev);
         return hipGetLastError();
     });
 }

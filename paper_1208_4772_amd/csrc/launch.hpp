@@ -29,6 +29,16 @@ struct DevMesh {
     bool bf3 = false;              // FP32 handle whose stage product runs as BF16x3
     bool av = false;
     int riemann = 0;               // numerical flux: 0 local Lax-Friedrichs, 1 HLLC
+    bool weak = false;             // the over-integrated weak form instead of the nodal form
+    // weak-form tables (weak.hip): operators Icub | Drc | Dsc | wq | If | Minv,
+    // straight-element metrics [K][5], face data [K][3][NG][3], curved
+    // elements' mapped cubature weights [Kc][NQ][4] and inverse mass matrices
+    const double *wops64 = nullptr, *wgeoA64 = nullptr, *wgeoF64 = nullptr, *wgeoC64 = nullptr,
+                 *wminv64 = nullptr;
+    const float *wops32 = nullptr, *wgeoA32 = nullptr, *wgeoF32 = nullptr, *wgeoC32 = nullptr,
+                *wminv32 = nullptr;
+    const int *widx = nullptr;     // [K] curved slot of the weak-form tables or -1
+    int wKc = 0;
     double gamma = 1.4, cfl = 0.5;
     double qinf[4] = {1, 0, 0, 2.5};
     double av_s0 = 0, av_kappa = 1;
@@ -105,8 +115,25 @@ size_t mfma_args_bytes();
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
                     void *out, const void *eps = nullptr, const void *Q = nullptr);
 int mfma_tiles(const DevMesh &m);
-hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items, int nitems,
-                                   hipStream_t st);
+// Batched launches are persistent: a grid of as many workgroups as the
+// device holds resident at once (compute units x resident blocks per CU of
+// that kernel, a multiple of the 8 XCDs) walks a work list whose length
+// the kernels read from device memory, so that a captured launch stays
+// valid when solves join or leave; every block is resident, so the static
+// split of the list keeps the blocks balanced.
+template <typename K>
+int resident_grid(K kernel, int block_threads) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block_threads, 0) != hipSuccess || per <= 0)
+        per = 1;
+    const int g = ncu * per / 8 * 8;
+    return g < 8 ? 8 : g;
+}
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items,
+                                   const int *nitems_dev, hipStream_t st);
 // CFL bound of state U (FP64) into the kVmaxSlots slots at *slot as bit
 // patterns (the maximum over them is the bound); raises *flag on bad states.
 // FP32 handles take the matrix-core kernel's own per-node bound
@@ -144,8 +171,8 @@ size_t av_args_bytes();
 void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned long long *vmax, void *out);
 // items: (job, tile) pairs of the stage kernel's tiles; eitems: (job, block)
 // pairs of blocks of 256 elements for the per-element sensor
-hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, int nitems,
-                           const void *eitems, int neitems, hipStream_t st);
+hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, const int *nitems_dev,
+                           const void *eitems, const int *neitems_dev, hipStream_t st);
 int sensor_elem_blocks(const DevMesh &m);
 // CFL reduction -> scal[S_DT] (dt_fixed > 0 overrides), accumulates S_T,
 // S_DTMIN/MAX, S_STEPS; raises *flag on bad states.
@@ -158,6 +185,13 @@ hipError_t launch_residual(const DevMesh &m, const void *rhs, hipStream_t st);
 // eps (state precision) -> double
 hipError_t launch_eps_to_double(const DevMesh &m, const void *eps, double *out, hipStream_t st);
 hipError_t launch_reset_scalars(const DevMesh &m, hipStream_t st);
+// over-integrated weak form (weak.hip)
+size_t weak_ops_size(int P);
+hipError_t launch_weak_geometry(const DevMesh &m, const double *x, const double *y, const double *Drg,
+                                const double *Dsg, const double *wg, double *geoA, double *geoF, double *geoC,
+                                double *mass, double *work, hipStream_t st);
+hipError_t launch_stage_weak(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                             hipStream_t st);
 // p-refinement: U_to [K][4][np_to] = I (np_to x np_from, row-major, host) U_from
 constexpr int kProlongMax = 21 * 21;
 hipError_t launch_prolong(int K, int np_from, int np_to, const double *I, bool fp32, const void *Uf, void *Ut,

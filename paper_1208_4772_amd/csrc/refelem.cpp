@@ -184,7 +184,109 @@ std::vector<double> transpose(const std::vector<double> &A, int m, int n) {
     return T;
 }
 
+// Gauss points of the weight (1-x)^a (1+x)^b on [-1,1] (n points): the
+// roots of p_n^(a,b) by Newton's method from Chebyshev guesses, with the
+// Christoffel weights 1 / sum_{k<n} p_k(x)^2 of the orthonormal polynomials.
+void gauss_jacobi(int n, double a, double b, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            const double f = jacobi(z, a, b, n), df = jacobi_deriv(z, a, b, n);
+            const double dz = f / df;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+    }
+    std::sort(x.begin(), x.end());
+    for (int i = 0; i < n; ++i) {
+        double sum = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double p = jacobi(x[i], a, b, k);
+            sum += p * p;
+        }
+        w[i] = 1.0 / sum;
+    }
+}
+
 }  // namespace
+
+bool build_weak(int P, WeakOps &w) {
+    RefOps o;
+    if (!build_reference(P, o)) return false;
+    const int Np = o.Np, Nfp = o.Nfp, n = weak_points_per_direction(P);
+    w.P = P;
+    w.Np = Np;
+    w.Nfp = Nfp;
+    w.n = n;
+    w.ncub = n * n;
+    w.ng = n;
+    std::vector<double> a, wa, b, wb;
+    gauss_jacobi(n, 0.0, 0.0, a, wa);
+    gauss_jacobi(n, 1.0, 0.0, b, wb);
+    std::vector<int> mi, mj;
+    for (int d = 0; d <= P; ++d)
+        for (int i = 0; i <= d; ++i) {
+            mi.push_back(i);
+            mj.push_back(d - i);
+        }
+    // basis (and derivatives) at points (r, s): modal values times V^{-1}
+    auto nodal_at = [&](const std::vector<double> &r, const std::vector<double> &s, std::vector<double> &phi,
+                        std::vector<double> &dphr, std::vector<double> &dphs) {
+        const int m = int(r.size());
+        std::vector<double> Vq(size_t(m) * Np), Vr(size_t(m) * Np), Vs(size_t(m) * Np);
+        for (int p = 0; p < m; ++p)
+            for (int k = 0; k < Np; ++k) {
+                double v, dr, ds;
+                mode(r[p], s[p], mi[k], mj[k], v, dr, ds);
+                Vq[p * Np + k] = v;
+                Vr[p * Np + k] = dr;
+                Vs[p * Np + k] = ds;
+            }
+        phi = matmul(Vq, o.Vinv, m, Np, Np);
+        dphr = matmul(Vr, o.Vinv, m, Np, Np);
+        dphs = matmul(Vs, o.Vinv, m, Np, Np);
+    };
+    std::vector<double> rq, sq;
+    w.wq.clear();
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            rq.push_back(0.5 * (1.0 + a[i]) * (1.0 - b[j]) - 1.0);
+            sq.push_back(b[j]);
+            w.wq.push_back(0.5 * wa[i] * wb[j]);
+        }
+    nodal_at(rq, sq, w.Icub, w.Drc, w.Dsc);
+    w.tg = a;
+    w.wg = wa;
+    // face nodes' 1D Lagrange basis at the Gauss points, through the
+    // orthonormal Legendre Vandermonde of the face-node parameters
+    std::vector<double> tn(Nfp);
+    for (int j = 0; j < Nfp; ++j) tn[j] = o.r[o.fmask[j]];   // face 0: t = r
+    std::vector<double> V1(size_t(Nfp) * Nfp), Vg(size_t(n) * Nfp);
+    for (int j = 0; j < Nfp; ++j)
+        for (int k = 0; k < Nfp; ++k) V1[j * Nfp + k] = jacobi(tn[j], 0.0, 0.0, k);
+    for (int g = 0; g < n; ++g)
+        for (int k = 0; k < Nfp; ++k) Vg[g * Nfp + k] = jacobi(a[g], 0.0, 0.0, k);
+    if (!invert(V1, Nfp)) return false;
+    w.If = matmul(Vg, V1, n, Nfp, Nfp);
+    w.Drg.clear();
+    w.Dsg.clear();
+    for (int f = 0; f < 3; ++f) {
+        std::vector<double> rg(n), sg(n), phi, dr, ds;
+        for (int g = 0; g < n; ++g) {
+            const double t = a[g];
+            rg[g] = f == 0 ? t : (f == 1 ? -t : -1.0);
+            sg[g] = f == 0 ? -1.0 : (f == 1 ? t : -t);
+        }
+        nodal_at(rg, sg, phi, dr, ds);
+        w.Drg.insert(w.Drg.end(), dr.begin(), dr.end());
+        w.Dsg.insert(w.Dsg.end(), ds.begin(), ds.end());
+    }
+    w.Minv = matmul(o.V, transpose(o.V, Np, Np), Np, Np, Np);
+    return true;
+}
 
 bool build_reference(int P, RefOps &o) {
     if (P < 1 || P > 5) return false;

@@ -196,21 +196,22 @@ __device__ __forceinline__ double node_cfl(double gamma, const float (&uf)[4], i
     double u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = double(uf[c]);
-    if (bad_state(gamma, u)) bad = 1;
     constexpr NodeFaceTable<P> kNF;
     const int nq = kNF.v[in];
-    if (!nq) return 0.0;
-    const int q0 = (nq & 255) - 1, q1 = (nq >> 8) - 1;
-    float fs;
-    if (!gc) {
-        fs = g16[6 + 3 * (q0 / Nfp)];
-        if (q1 >= 0) fs = fmaxf(fs, g16[6 + 3 * (q1 / Nfp)]);
-    } else {
-        const float *gf = gc + 4 * Np + 2 * NF3;
-        fs = gf[q0];
-        if (q1 >= 0) fs = fmaxf(fs, gf[q1]);
+    // an interior node (on no face) takes Fscale 0: only its state check
+    float fs = 0.f;
+    if (nq) {
+        const int q0 = (nq & 255) - 1, q1 = (nq >> 8) - 1;
+        if (!gc) {
+            fs = g16[6 + 3 * (q0 / Nfp)];
+            if (q1 >= 0) fs = fmaxf(fs, g16[6 + 3 * (q1 / Nfp)]);
+        } else {
+            const float *gf = gc + 4 * Np + 2 * NF3;
+            fs = gf[q0];
+            if (q1 >= 0) fs = fmaxf(fs, gf[q1]);
+        }
     }
-    return cfl_bound(gamma, u, double(fs), 0.0, P + 1.0);
+    return cfl_bound_checked(gamma, u, double(fs), 0.0, P + 1.0, bad);
 }
 
 // One tile (EB consecutive elements) of one mesh.  `a` may live in kernel
@@ -662,12 +663,19 @@ void k_stage_mfma(MfmaArgs a) {
 // argument record for this stage.
 template <int P, bool BF3, int W, bool AV>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W, AV>())))
-void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restrict__ items, int nitems,
-                        int chunk) {
-    const int w = xcd_item(chunk);
-    if (w >= nitems) return;
-    const int2 it = items[w];
-    stage_tile<P, BF3, W, AV>(jobs[it.x], it.y);
+void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restrict__ items,
+                        const int *__restrict__ nitems_dev) {
+    // persistent over the work list, whose length is read from device
+    // memory (a captured launch stays valid when the list changes); each
+    // XCD (block b runs on XCD b % 8) sweeps a contiguous eighth of it
+    const int n = *nitems_dev;
+    const int per = (n + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
+    const int end = min(n, (x + 1) * per);
+    for (int w = x * per + int(blockIdx.x / 8); w < end; w += stride) {
+        const int2 it = items[w];
+        stage_tile<P, BF3, W, AV>(jobs[it.x], it.y);
+        __syncthreads();   // the next item reuses the LDS
+    }
 }
 
 template <int P>
@@ -854,24 +862,26 @@ int mfma_tiles(const DevMesh &m) {
     return (m.K + eb - 1) / eb;
 }
 
-hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items, int nitems,
-                                   hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
-    const int chunk = (nitems + 7) / 8;
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items,
+                                   const int *nitems_dev, hipStream_t st) {
     const auto *j = static_cast<const MfmaArgs *>(jobs);
     const auto *it = static_cast<const int2 *>(items);
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
         constexpr int W = default_waves(PP);
-        const dim3 grid(8 * chunk), block(64 * W);
+        const dim3 block(64 * W);
+        auto go = [&](auto kern) {
+            static const int g = resident_grid(kern, 64 * W);
+            hipLaunchKernelGGL(kern, dim3(g), block, 0, st, j, it, nitems_dev);
+        };
         if (bf3 && av)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, true>), grid, block, 0, st, j, it, nitems, chunk);
+            go(k_stage_mfma_batch<PP, true, W, true>);
         else if (bf3)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, false>), grid, block, 0, st, j, it, nitems, chunk);
+            go(k_stage_mfma_batch<PP, true, W, false>);
         else if (av)
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, true>), grid, block, 0, st, j, it, nitems, chunk);
+            go(k_stage_mfma_batch<PP, false, W, true>);
         else
-            hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, false>), grid, block, 0, st, j, it, nitems, chunk);
+            go(k_stage_mfma_batch<PP, false, W, false>);
         return hipGetLastError();
     });
 }

@@ -24,6 +24,8 @@ PRECISIONS = {"fp64": DG_FP64_PLAIN, "fp64_plain": DG_FP64_PLAIN, "fp32": DG_FP3
               "bf16x3": DG_FP32_BF16X3}
 DG_RIEMANN_LF, DG_RIEMANN_HLLC = 0, 1
 RIEMANN = {"lf": DG_RIEMANN_LF, "hllc": DG_RIEMANN_HLLC}
+DG_FORM_NODAL, DG_FORM_WEAK = 0, 1
+FORMS = {"nodal": DG_FORM_NODAL, "weak": DG_FORM_WEAK}
 
 # Every symbol include/dg.h declares.
 EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
@@ -32,7 +34,8 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_set_graphs", "dg_set_kernel_timing", "dg_kernel_time", "dg_autotune", "dg_mesh_footprint",
            "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
-           "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong")
+           "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong", "dg_weak_operators",
+           "dg_batch_info")
 
 
 class DGError(RuntimeError):
@@ -48,7 +51,7 @@ class MeshDesc(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p),
                 ("freestream", C.c_double * 4),
                 ("av_enable", C.c_int), ("av_eps0", C.c_double), ("av_s0", C.c_double),
-                ("av_kappa", C.c_double), ("riemann", C.c_int)]
+                ("av_kappa", C.c_double), ("riemann", C.c_int), ("form", C.c_int)]
 
 
 class RunStats(C.Structure):
@@ -85,6 +88,7 @@ def lib():
         L.dg_step.argtypes = [vp, vp, vp, d, vp]
         L.dg_step_static.argtypes = [vp, vp, d, vp]
         L.dg_prolong_operator.argtypes = [i, i, vp]
+        L.dg_weak_operators.argtypes = [i, C.POINTER(i), C.POINTER(i), vp, vp, vp, vp, vp, vp]
         L.dg_prolong.argtypes = [vp, vp, vp, vp, vp]
         L.dg_run.argtypes = [vp, vp, vp, i, C.POINTER(RunStats), vp]
         L.dg_totals.argtypes = [vp, vp, vp, vp]
@@ -103,6 +107,7 @@ def lib():
         L.dg_batch_poll.argtypes = [vp, vp, vp, i, C.POINTER(i)]
         L.dg_batch_slot_stats.argtypes = [vp, i, vp, C.POINTER(RunStats)]
         L.dg_batch_release.argtypes = [vp, i]
+        L.dg_batch_info.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
         L.dg_kernel_time.argtypes = [vp, vp, C.POINTER(d), C.POINTER(C.c_long)]
         L.dg_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(i), C.POINTER(d)]
         for name in EXPORTS:
@@ -150,6 +155,18 @@ def reference_operators(P: int):
     return dict(Dr=Dr, Ds=Ds, LIFT=LIFT, Vinv=Vinv)
 
 
+def weak_operators(P: int):
+    """The library's weak-form operators of order P (host arrays)."""
+    nq, ng = C.c_int(), C.c_int()
+    _check(lib().dg_weak_operators(int(P), C.byref(nq), C.byref(ng), None, None, None, None, None, None))
+    Np, Nfp = n_nodes(P), P + 1
+    out = dict(wq=np.zeros(nq.value), Icub=np.zeros((nq.value, Np)), Drc=np.zeros((nq.value, Np)),
+               Dsc=np.zeros((nq.value, Np)), wg=np.zeros(ng.value), If=np.zeros((ng.value, Nfp)))
+    _check(lib().dg_weak_operators(int(P), C.byref(nq), C.byref(ng), *(_p(out[k]) for k in
+                                                                       ("wq", "Icub", "Drc", "Dsc", "wg", "If"))))
+    return out
+
+
 def prolong_operator(P: int, Q: int):
     """(Np(Q), Np(P)) prolongation matrix of the library (p-refinement)."""
     I = np.zeros((n_nodes(Q), n_nodes(P)))
@@ -183,7 +200,7 @@ class Solver:
 
     def __init__(self, EToE, EToF, bc, x, y, P, precision="fp32", gamma=1.4, cfl=0.5,
                  freestream=(1.0, 0.0, 0.0, 2.5), av=False, av_eps0=0.3, av_s0=float("nan"),
-                 av_kappa=1.0, riemann="lf", device="cuda:0"):
+                 av_kappa=1.0, riemann="lf", form="nodal", device="cuda:0"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -213,6 +230,9 @@ class Solver:
         if riemann not in RIEMANN:
             raise ValueError(f"riemann must be one of {sorted(RIEMANN)}")
         d.riemann = RIEMANN[riemann]
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
+        d.form = FORMS[form]
         self.av = bool(av)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -414,6 +434,12 @@ class Batch:
         _check(lib().dg_batch_slot_stats(self._h, int(slot), _stream_handle(stream), C.byref(st)))
         return Stats(st.steps, st.status, st.t, st.dt_min, st.dt_max, tuple(st.totals),
                      tuple(st.residual), st.wall_s, st.dof_updates_per_s)
+
+    def info(self):
+        """(graphs captured so far, kinds of solve with tables)."""
+        c, g = C.c_int(), C.c_int()
+        _check(lib().dg_batch_info(self._h, C.byref(c), C.byref(g)))
+        return c.value, g.value
 
     def release(self, slot):
         _check(lib().dg_batch_release(self._h, int(slot)))

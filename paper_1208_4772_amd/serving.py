@@ -131,7 +131,7 @@ class Report:
                     makespan_s=float(last - first), peak_slots=self.peak_slots,
                     budget_bytes=self.budget, max_slots=self.max_slots,
                     chunk_steps=self.chunk_steps, busy_rejections=self.busy_rejections,
-                    failed=int(sum(1 for r in self.requests if r.status != 0)))
+                    failed=int(sum(1 for r in self.requests if r.status != 0)), **self.extra)
 
 
 class Server:
@@ -219,9 +219,11 @@ class Server:
                           f"{len(active)} active, {len(queue)} queued")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        captures, kinds = batch.info()
         batch.close()
         return Report(list(requests), wall, self.precision, self.budget, self.max_slots,
-                      self.chunk_steps, peak, rejections)
+                      self.chunk_steps, peak, rejections,
+                      extra=dict(graph_captures=captures, solve_kinds=kinds))
 
 
 def main(argv=None):

@@ -97,3 +97,60 @@ def test_admission_by_footprint():
     slots = dg().Batch(1 << 34, 1)
     assert slots.admit(s1, U1, 2) is not None
     assert slots.admit(s2, U2, 2) is None       # no free slot
+
+
+def test_joins_and_leaves_of_known_kinds_do_not_recapture():
+    """The batched launches read their work lists' lengths from device
+    memory: once the kinds of solve (order, precision, viscosity) present
+    have been captured, solves joining and leaving reuse the graph; a new
+    kind captures once more.  Results stay those of the solves alone."""
+    import torch
+    b = dg().Batch(1 << 34, 8)
+    kinds = [("cylinder", 3, 0.02, "fp32", 0.4, False), ("airfoil", 2, 0.01, "fp32", 0.6, True)]
+    live = {}
+
+    def admit(kind, P, scale, prec, mach, av, steps):
+        case, sol = make(kind, P, scale, prec, mach, av)
+        U = sol.state(case.U0)
+        slot = b.admit(sol, U, steps)
+        assert slot is not None
+        live[slot] = ((kind, P, scale, steps, prec, mach, av), sol, U)
+
+    for k in kinds:
+        admit(*k, 6)
+    results = []
+    captures = []
+    for round_ in range(4):
+        while live:
+            b.advance(4)
+            for slot in b.poll():
+                req, sol, U = live.pop(slot)
+                results.append((req, U.double().cpu().numpy()))
+                b.release(slot)
+            captures.append(b.info()[0])
+        # the same kinds again, other sizes and step counts
+        for k in kinds:
+            kind, P, scale, prec, mach, av = k
+            admit(kind, P, scale * (1.2 + 0.3 * round_), prec, mach, av, 6 + 2 * round_)
+    while live:
+        b.advance(4)
+        for slot in b.poll():
+            req, sol, U = live.pop(slot)
+            results.append((req, U.double().cpu().numpy()))
+            b.release(slot)
+    torch.cuda.synchronize()
+    ncap, ngroups = b.info()
+    assert ngroups == 2
+    assert ncap == 1, captures
+    # a new kind (another order) captures once more
+    admit("cylinder", 4, 0.02, "fp32", 0.4, False, 4)
+    while live:
+        b.advance(4)
+        for slot in b.poll():
+            req, sol, U = live.pop(slot)
+            results.append((req, U.double().cpu().numpy()))
+            b.release(slot)
+    assert b.info() == (2, 3)
+    for req, Ub in results:
+        Ua, _ = run_alone(*req)
+        assert np.array_equal(Ua, Ub), req

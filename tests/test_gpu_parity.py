@@ -712,3 +712,69 @@ def test_p_refinement_continuation_matches_oracle():
     assert err <= 10 * FP64_TOL
     assert abs(res.legs[0].t - i2["t"]) <= 1e-12 * i2["t"]
     assert abs(res.legs[1].t - i3["t"]) <= 1e-12 * i3["t"]
+
+
+def weak_cases():
+    qv = np.array([1.0, 1.0, 0.0, 1.0 / 0.4 + 0.5])
+    return [
+        ("curved_periodic_P2", lambda: meshgen.periodic_square(5, perm_seed=11, curved_amplitude=0.05), 2, qv),
+        ("curved_periodic_P5", lambda: meshgen.periodic_square(5, perm_seed=11, curved_amplitude=0.05), 5, qv),
+        ("cylinder_small_P3", lambda: meshgen.cylinder_annulus(24, 6), 3, meshgen.freestream_state(0.38)),
+        ("airfoil_small_P4", lambda: meshgen.naca4_ogrid(40, 8), 4, meshgen.freestream_state(0.7, 1.25)),
+        ("supersonic_farfield_P1", lambda: meshgen.cylinder_annulus(24, 4, R2=3.0, inner_bc=meshgen.BC_FARFIELD),
+         1, meshgen.freestream_state(1.5, 5.0)),
+        ("vortex_config_P2", lambda: meshgen.periodic_square(16), 2, qv),
+    ]
+
+
+@pytest.mark.parametrize("name,mk,P,q", weak_cases(), ids=[c[0] for c in weak_cases()])
+@pytest.mark.parametrize("riemann", ["lf", "hllc"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_weak_form_rhs_matches_oracle(name, mk, P, q, riemann, precision):
+    """The over-integrated weak form on the GPU against the oracle's."""
+    mesh = mk()
+    R = ref(P)
+    x, y = meshgen.node_coordinates(mesh, R.r, R.s)
+    o = orc.Oracle(mesh, P, x, y, freestream=q, riemann=riemann, weak=True)
+    s = dg().Solver(mesh.EToE, mesh.EToF, mesh.bc, x, y, P, precision, freestream=q, riemann=riemann,
+                    form="weak")
+    U = perturbed_state(x, y, q)
+    ref_rhs = o.rhs(U)
+    got = s.rhs(s.state(U)).double().cpu().numpy()
+    err = rel_l2(got, ref_rhs)
+    tol = TOL[precision]
+    if precision == "fp32":
+        # the weak form cancels more than the nodal one (V - S of nearly
+        # equal volume and surface integrals): the FP64 kernel's distance
+        # from the oracle on the same input measures that conditioning, and
+        # the same operations in FP32 round 2^29 times coarser
+        s64 = dg().Solver(mesh.EToE, mesh.EToF, mesh.bc, x, y, P, "fp64", freestream=q, riemann=riemann,
+                          form="weak")
+        e64 = rel_l2(s64.rhs(s64.state(U)).cpu().numpy(), ref_rhs)
+        s64.close()
+        tol = max(tol, 2.0 ** 29 * e64)
+    print(f"[weak {name} {riemann} {precision}] K={mesh.K} rel L2 {err:.3e} (bar {tol:.1e})")
+    assert err <= tol
+    assert_subsets(mesh, got, ref_rhs, tol, None, f"weak {name} {precision}")
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_weak_form_vortex_run_matches_oracle(precision):
+    """100 CFL steps of the isentropic vortex configuration (512 permuted,
+    jittered triangles, P = 2) in the weak form: state and time."""
+    import torch
+    P = 2
+    R = ref(P)
+    case = meshgen.make_case("vortex", R.r, R.s)
+    o = orc.Oracle.for_case(case, weak=True)
+    s = dg().Solver.from_case(case, precision, form="weak")
+    Ur, info = o.run(case.U0, case.steps)
+    Ud = s.state(case.U0)
+    st = s.run(Ud, case.steps)
+    torch.cuda.synchronize()
+    got = Ud.double().cpu().numpy()
+    err = rel_l2(got, Ur)
+    print(f"[weak vortex {precision}] rel L2 {err:.3e}")
+    assert err <= RUN_TOL[precision]
+    assert abs(st.t - info["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * info["t"]

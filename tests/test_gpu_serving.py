@@ -18,6 +18,11 @@ def test_server_runs_mix_and_matches_alone():
     assert s["failed"] == 0 and s["n_requests"] == 8, [(r.rid, r.status) for r in reqs]
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
     assert 1 <= rep.peak_slots <= 4
+    # the step graph is captured again only when a new kind of solve
+    # (order; all requests here are FP32 and viscous) joins, not at every
+    # admission or release
+    kinds = len({r.P for r in reqs})
+    assert s["solve_kinds"] == kinds and s["graph_captures"] <= kinds, s
     for r in reqs[:3]:
         sol = dg.Solver.from_case(r.case, "fp32")
         U = sol.state(r.case.U0)

@@ -105,3 +105,15 @@ def test_one_hip_runtime_in_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
                          cwd=ROOT)
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5])
+def test_library_weak_operators_match_oracle(P):
+    """The library's cubature rule and weak-form operators (C++ Newton roots,
+    Christoffel weights) against the oracle's (SciPy Gauss rules)."""
+    from oracle.refelem import weak_ops
+    L = dg.weak_operators(P)
+    W = weak_ops(P)
+    for name in ("wq", "Icub", "Drc", "Dsc", "wg", "If"):
+        ref_op = getattr(W, name)
+        np.testing.assert_allclose(L[name], ref_op, atol=1e-13 * max(1.0, np.abs(ref_op).max()))

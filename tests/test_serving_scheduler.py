@@ -63,6 +63,9 @@ class FakeBatch:
         FakeBatch.log.append(("release", self.slots[slot][0].case.rid))
         del self.slots[slot]
 
+    def info(self):
+        return 1, 1
+
     def close(self):
         pass
 
