@@ -260,18 +260,43 @@ int dg_set_kernel_timing(dg_mesh *mesh, int enable);
 
 /* Autotuner for the workgroup shape of the FP32 matrix-core stage kernel:
  * elements per workgroup = 2, 4 or 8 wavefronts times the elements one
- * wavefront holds (floor(64 / Np)).  Times each candidate over Runge-Kutta
- * stage evaluations of the device state U [K][4][Np] (written into the work
- * buffer, whose contents between steps are scratch; U is only read) and
- * keeps the fastest for this handle (results do not depend on the choice).  *waves_per_block
- * receives the choice and *stage_us the measured time of one launch (either
- * may be NULL).  Handles without the matrix-core kernel (FP64, artificial
- * viscosity) return DG_OK with 0.  Batches keep the default shape (4
- * wavefronts).
+ * wavefront holds (floor(64 / Np)).  The shape is a launch parameter, not
+ * part of the method: results do not depend on it.
+ * If the process tuning table (below) holds a shape for this handle's kind
+ * (device architecture, P, precision, viscosity), applies it and returns it
+ * with *stage_us = 0 without timing.  Otherwise times each candidate over
+ * Runge-Kutta stage evaluations of the device state U [K][4][Np] (written
+ * into the work buffer, whose contents between steps are scratch; U is only
+ * read; a viscous handle's viscosity and sigma grad U of U are computed
+ * there first), keeps the fastest for this handle and records it in the
+ * table.  *waves_per_block receives the choice and *stage_us the measured
+ * time of one launch (either may be NULL).  FP64 and weak-form handles have
+ * no shape to tune and return DG_OK with 0.
  * Synchronises the stream.  Errors: DG_EINVAL, DG_EDEVICE. */
 int dg_autotune(dg_mesh *mesh, const void *U, void *work, void *stream, int *waves_per_block,
                 double *stage_us);
 int dg_kernel_time(dg_mesh *mesh, void *stream, double *stage_ms_total, long *stage_launches);
+
+/* Tuning table: one workgroup shape (waves per workgroup: 2, 4 or 8) per
+ * (device architecture name such as "gfx950", P, precision DG_FP32 or
+ * DG_FP32_BF16X3, av_enable 0/1), process-wide and thread-safe.  A new
+ * handle takes its kind's entry (unless the environment variable
+ * DG_WAVES_PER_BLOCK sets the shape); a batch takes it for a kind of solve
+ * when that kind first joins the batch and keeps it for the batch's life.
+ * dg_autotune fills it; dg_tuning_save/dg_tuning_load persist it as text,
+ * one entry per line: "arch P precision av waves stage_us" ('#' starts a
+ * comment line); a load merges into the table and rejects the whole file
+ * (DG_EINVAL, naming the line) if any entry is malformed.  *entries (may be
+ * NULL) receives the number of entries written or read.  dg_tuning_lookup
+ * gives 0 for a kind with no entry; dg_device_arch writes the current
+ * device's architecture name (NUL-terminated; DG_EINVAL if size is too
+ * small).  Errors: DG_EINVAL. */
+int dg_tuning_set(const char *arch, int P, int precision, int av_enable, int waves_per_block);
+int dg_tuning_lookup(const char *arch, int P, int precision, int av_enable, int *waves_per_block);
+int dg_tuning_clear(void);
+int dg_tuning_save(const char *path, int *entries);
+int dg_tuning_load(const char *path, int *entries);
+int dg_device_arch(char *buf, size_t size);
 
 /* Device bytes a handle holds (geometry, operators, scratch) plus one state
  * array and its work buffer: the unit of HBM-footprint admission. */

@@ -20,7 +20,7 @@ paragraphs):
   C_D = (F_x cos a + F_y sin a) / (q_inf c), C_L = (-F_x sin a + F_y cos a) /
   (q_inf c), q_inf = rho_inf |v_inf|^2 / 2;
 * shock position: on the upper surface (wall nodes with y > 0), ordered by
-  x, the first place where the pressure coefficient rises through the
+  x, the last place where the pressure coefficient rises through the
   critical value C_p* = 2 / (gamma M^2) [((2 + (gamma-1) M^2) / (gamma+1))
   ^(gamma/(gamma-1)) - 1], linearly interpolated between the two nodes.
 """
@@ -128,11 +128,14 @@ def upper_surface_cp(o, U, freestream, gamma=1.4):
 
 
 def shock_position(o, U, freestream, mach, gamma=1.4):
-    """x of the first upward crossing of C_p* on the upper surface (NaN if
-    the pressure coefficient never rises through it)."""
+    """x of the last upward crossing of C_p* on the upper surface, linear
+    between wall nodes (NaN if the pressure coefficient never rises through
+    it).  Behind the shock the flow stays subsonic to the trailing edge;
+    earlier crossings are pressure wiggles near the leading edge."""
     xs, cs = upper_surface_cp(o, U, freestream, gamma)
     cstar = critical_cp(mach, gamma)
+    x = float("nan")
     for i in range(xs.size - 1):
         if cs[i] < cstar <= cs[i + 1]:
-            return float(xs[i] + (cstar - cs[i]) / (cs[i + 1] - cs[i]) * (xs[i + 1] - xs[i]))
-    return float("nan")
+            x = float(xs[i] + (cstar - cs[i]) / (cs[i + 1] - cs[i]) * (xs[i + 1] - xs[i]))
+    return x

@@ -11,7 +11,8 @@ resulting states back and evaluates diagnostics on the host:
 * wall loads: lift and drag coefficients from the pressure integral over
   the wall faces (Gauss-Lobatto quadrature on the face nodes of the curved
   geometry), the minimum pressure coefficient and, on the upper surface,
-  the chordwise position of the steepest pressure rise (the shock);
+  the shock position: the last upward crossing of the critical pressure
+  coefficient C_p* (the flow behind it is subsonic to the trailing edge);
 * freestream preservation on an all-curved mesh (a uniform state must stay
   uniform up to rounding) and the drift of the conserved totals on a
   periodic mesh.
@@ -31,6 +32,12 @@ import meshgen
 from . import dg
 
 GAMMA = 1.4
+
+
+def critical_cp(mach, gamma=GAMMA):
+    """Pressure coefficient at which the isentropic local Mach number is 1."""
+    g = gamma
+    return 2.0 / (g * mach * mach) * (((2.0 + (g - 1.0) * mach * mach) / (g + 1.0)) ** (g / (g - 1.0)) - 1.0)
 
 
 # -- host geometry -----------------------------------------------------------
@@ -103,10 +110,11 @@ class Geometry:
             yw.append(ye)
         self._wall = list(zip(nodes, wts, nx, ny, xw, yw))
 
-    def wall_loads(self, U, freestream, gamma=GAMMA, upper_x=(0.2, 0.95)):
+    def wall_loads(self, U, freestream, gamma=GAMMA):
         """Pressure force on the walls as lift/drag coefficients (reference
         length 1), the minimum pressure coefficient and the upper-surface
-        shock position (steepest pressure rise); None without walls."""
+        shock position (last upward crossing of C_p*, NaN without one);
+        None without walls."""
         if not self._wall:
             return None
         q = np.asarray(freestream, dtype=np.float64)
@@ -114,6 +122,7 @@ class Geometry:
         V2 = u0 * u0 + v0 * v0
         p0 = (gamma - 1.0) * (q[3] - 0.5 * rho0 * V2)
         qdyn = 0.5 * rho0 * V2
+        mach = math.sqrt(V2 / (gamma * p0 / rho0))
         Fx = Fy = 0.0
         xs_all, ys_all, cps = [], [], []
         for (ke, ids), w, nx, ny, xe, ye in self._wall:
@@ -130,17 +139,18 @@ class Geometry:
         CD = (Fx * ca + Fy * sa) / qdyn
         CL = (-Fx * sa + Fy * ca) / qdyn
         xw, yw, cp = np.concatenate(xs_all), np.concatenate(ys_all), np.concatenate(cps)
-        out = dict(CL=CL, CD=CD, cp_min=float(cp.min()))
-        up = (yw > 0) & (xw > upper_x[0]) & (xw < upper_x[1])
-        if up.sum() > 4:
-            order = np.argsort(xw[up])
+        out = dict(CL=CL, CD=CD, cp_min=float(cp.min()), shock_x=float("nan"))
+        up = yw > 0
+        if up.sum() > 1:
+            order = np.argsort(xw[up], kind="stable")
             xu, cu = xw[up][order], cp[up][order]
-            keep = np.concatenate([[True], np.diff(xu) > 1e-9])
+            keep = np.concatenate([[True], np.diff(xu) > 1e-12])
             xu, cu = xu[keep], cu[keep]
-            dcp = np.diff(cu) / np.diff(xu)
-            i = int(np.argmax(dcp))
-            out["shock_x"] = float(0.5 * (xu[i] + xu[i + 1]))
-            out["shock_dcp_dx"] = float(dcp[i])
+            cstar = critical_cp(mach, gamma)
+            ups = np.nonzero((cu[:-1] < cstar) & (cu[1:] >= cstar))[0]
+            if ups.size:
+                i = int(ups[-1])
+                out["shock_x"] = float(xu[i] + (cstar - cu[i]) / (cu[i + 1] - cu[i]) * (xu[i + 1] - xu[i]))
         return out
 
     def entropy_error(self, U, freestream, gamma=GAMMA):

@@ -68,7 +68,9 @@ def run(make_solver, U0, orders, check_every=1000, switch_residual=1e-4, final_r
     residual of the state it reached; it moves to the next order once the
     residual is at most `switch_residual` (a float, or a dict per order),
     and stops at the last order once it is at most `final_residual`, or at
-    any order after `max_steps_per_order` steps.  A state check failure
+    any order after `max_steps_per_order` steps (an int, or a dict per
+    order: the paper fixes the iterations of its lower orders by hand, with
+    a switch residual of 0 that is the same).  A state check failure
     (non-finite state, rho <= 0 or p <= 0) stops the continuation with
     status DG_ENONFINITE."""
     orders = list(orders)
@@ -90,8 +92,9 @@ def run(make_solver, U0, orders, check_every=1000, switch_residual=1e-4, final_r
                                               else switch_residual)
         leg = OrderLeg(P)
         legs.append(leg)
-        while leg.steps < max_steps_per_order:
-            k = min(check_every, max_steps_per_order - leg.steps)
+        limit = max_steps_per_order[P] if isinstance(max_steps_per_order, dict) else max_steps_per_order
+        while leg.steps < limit:
+            k = min(check_every, limit - leg.steps)
             t0 = time.perf_counter()
             st = solver.run(U, k, stream=stream, check=False)
             leg.wall_s += time.perf_counter() - t0
@@ -131,25 +134,35 @@ def main(argv=None):
     ap.add_argument("--switch-residual", type=float, default=1e-4)
     ap.add_argument("--final-residual", type=float, default=1e-9)
     ap.add_argument("--max-steps", type=int, default=100000)
+    ap.add_argument("--steps-per-order", default=None,
+                    help="fixed iterations of the lower orders, e.g. 2:40000,3:40000 (no residual switch there)")
     ap.add_argument("--mach", type=float, default=0.38)
+    ap.add_argument("--form", default="nodal", choices=["nodal", "weak"])
+    ap.add_argument("--start", default="potential", choices=["potential", "freestream", "damped"])
     a = ap.parse_args(argv)
     orders = [int(p) for p in a.orders.split(",")]
 
     def case_at(P):
         r, s = dg.reference_nodes(P)
-        return meshgen.make_case("cylinder", r, s, scale=a.scale, P=P, mach=a.mach, start="potential")
+        return meshgen.make_case("cylinder", r, s, scale=a.scale, P=P, mach=a.mach, start=a.start)
 
     def make_solver(P):
-        return dg.Solver.from_case(case_at(P), a.precision)
+        return dg.Solver.from_case(case_at(P), a.precision, form=a.form)
 
+    switch, limits = a.switch_residual, a.max_steps
+    if a.steps_per_order:
+        fixed = {int(k): int(v) for k, v in (kv.split(":") for kv in a.steps_per_order.split(","))}
+        switch = {P: 0.0 for P in orders}
+        limits = {P: fixed.get(P, a.max_steps) for P in orders}
     out = {}
     for label, ords in (("p_refinement", orders), ("single_order", orders[-1:])):
         c0 = case_at(ords[0])
-        res = run(make_solver, c0.U0, ords, a.check_every, a.switch_residual, a.final_residual, a.max_steps)
+        res = run(make_solver, c0.U0, ords, a.check_every, switch, a.final_residual, limits)
         res.solver.close()
         out[label] = res.summary()
         print(json.dumps({label: out[label]}), flush=True)
     out["K"] = case_at(orders[0]).K
+    out["form"] = a.form
     print(json.dumps(out), flush=True)
 
 

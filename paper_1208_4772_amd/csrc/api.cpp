@@ -7,8 +7,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dg.h"
@@ -35,6 +39,36 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// ---- tuning table: the workgroup shape (waves per workgroup) of the FP32
+// matrix-core stage kernel per (device architecture, order, precision,
+// viscosity), filled by dg_autotune or from a file, applied to new handles
+// and to batch groups.  Process-wide, guarded by a mutex.
+using TuneKey = std::tuple<std::string, int, int, int>;   // arch, P, precision, av
+struct TuneEntry {
+    int waves = 0;
+    double stage_us = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+bool tunable_waves(int w) { return w == 2 || w == 4 || w == 8; }
+
+// "gfx950" from "gfx950:sramecc+:xnack-"
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a(p.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int tuned_waves(const std::string &arch, int P, int precision, int av) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey(arch, P, precision, av ? 1 : 0));
+    return it == g_tune.end() ? 0 : it->second.waves;
+}
 
 }  // namespace
 
@@ -410,10 +444,14 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         SETUP_TRY(hipGetDevice(&dev));
         SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         dm.ncu = ncu > 0 ? ncu : 256;
+        // workgroup shape: DG_WAVES_PER_BLOCK if set, else the tuning
+        // table's choice for this kind of handle, else the default
         if (const char *e = std::getenv("DG_WAVES_PER_BLOCK")) {
             const int w = std::atoi(e);
-            if (w == 2 || w == 4 || w == 8) dm.waves_per_block = w;
+            if (tunable_waves(w)) dm.waves_per_block = w;
         }
+        if (!dm.waves_per_block && !dm.weak)
+            dm.waves_per_block = tuned_waves(device_arch(), dm.P, d->precision, dm.av);
         SETUP_TRY(hipStreamSynchronize(st));
     }
     if (dm.weak) {
@@ -881,18 +919,41 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
     if (int rc = check_ptr(work, "work")) return rc;
     if (waves_per_block) *waves_per_block = 0;
     if (stage_us) *stage_us = 0.0;
-    if (!m->dm.fp32 || m->dm.av || m->dm.weak) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
+    if (!m->dm.fp32 || m->dm.weak) return DG_OK;   // only the matrix-core kernel has a launch shape to tune
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::string arch = device_arch();
+    // drop captured step graphs, which hold the old launch shape
+    auto set_shape = [&](int w) {
+        if (m->dm.waves_per_block != w && m->graph_exec) {
+            (void)hipGraphExecDestroy(m->graph_exec);
+            m->graph_exec = nullptr;
+            m->graph_U = m->graph_work = nullptr;
+        }
+        m->dm.waves_per_block = w;
+    };
+    if (const int cached = tuned_waves(arch, m->dm.P, m->precision, m->dm.av)) {
+        set_shape(cached);
+        if (waves_per_block) *waves_per_block = cached;
+        return DG_OK;
+    }
     // candidates: workgroups of 2, 4 and 8 wavefronts (2, 4 or 8 times the
     // elements one wavefront holds), each timed over the five Runge-Kutta
     // stages of a step as a run executes them (ping-pong buffers), reading
     // U and writing only the work buffer's A, B and R slots (scratch between
-    // steps: a step's first stage overwrites them without reading them)
+    // steps: a step's first stage overwrites them without reading them);
+    // a viscous handle's stage kernel reads the viscosity and sigma grad U
+    // of U, computed once here into the work buffer
     static const int kCand[3] = {2, 4, 8};
     char *w = static_cast<char *>(work);
     void *A = w + m->off_A(), *B = w + m->off_B(), *R = w + m->off_R();
+    void *eps = m->dm.av ? w + m->off_eps() : nullptr;
+    void *Q = m->dm.av ? w + m->off_Q() : nullptr;
     const void *in5[5] = {U, A, B, A, B};
     void *out5[5] = {A, B, A, B, A};
+    if (m->dm.av) {
+        HIP_TRY(launch_sensor(m->dm, U, eps, st));
+        HIP_TRY(launch_avgrad(m->dm, U, eps, Q, st));
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -902,10 +963,10 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
     // (ms per launch)
     auto time_one = [&](int c, int reps, float *ms_per) -> hipError_t {
         m->dm.waves_per_block = c;
-        hipError_t e = launch_stage_mfma(m->dm, in5[0], out5[0], R, nullptr, 0, MfmaStep(), st);
+        hipError_t e = launch_stage_mfma(m->dm, in5[0], out5[0], R, nullptr, 0, MfmaStep(), st, eps, Q);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = launch_stage_mfma(m->dm, in5[r % 5], out5[r % 5], R, nullptr, r % 5, MfmaStep(), st);
+            e = launch_stage_mfma(m->dm, in5[r % 5], out5[r % 5], R, nullptr, r % 5, MfmaStep(), st, eps, Q);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -937,19 +998,98 @@ int dg_autotune(dg_mesh *m, const void *U, void *work, void *stream, int *waves_
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc != DG_OK) {
-        m->dm.waves_per_block = saved;
-        return rc;
-    }
-    m->dm.waves_per_block = best;
-    // captured step graphs hold the old launch shape
-    if (m->graph_exec) {
-        (void)hipGraphExecDestroy(m->graph_exec);
-        m->graph_exec = nullptr;
-        m->graph_U = m->graph_work = nullptr;
+    m->dm.waves_per_block = saved;
+    if (rc != DG_OK) return rc;
+    set_shape(best);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[TuneKey(arch, m->dm.P, m->precision, m->dm.av ? 1 : 0)] = TuneEntry{best, 1e3 * best_ms};
     }
     if (waves_per_block) *waves_per_block = best;
     if (stage_us) *stage_us = 1e3 * best_ms;
+    return DG_OK;
+}
+
+int dg_tuning_set(const char *arch, int P, int precision, int av_enable, int waves_per_block) {
+    if (!arch || !*arch) return fail(DG_EINVAL, "arch is empty");
+    if (P < 1 || P > 5) return fail(DG_EINVAL, "P must be in 1..5");
+    if (precision != DG_FP32 && precision != DG_FP32_BF16X3)
+        return fail(DG_EINVAL, "only the FP32 matrix-core precisions have a workgroup shape");
+    if (!tunable_waves(waves_per_block)) return fail(DG_EINVAL, "waves_per_block must be 2, 4 or 8");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey(arch, P, precision, av_enable ? 1 : 0)] = TuneEntry{waves_per_block, 0.0};
+    return DG_OK;
+}
+
+int dg_tuning_lookup(const char *arch, int P, int precision, int av_enable, int *waves_per_block) {
+    if (!arch || !waves_per_block) return fail(DG_EINVAL, "null argument");
+    *waves_per_block = tuned_waves(arch, P, precision, av_enable);
+    return DG_OK;
+}
+
+int dg_tuning_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return DG_OK;
+}
+
+int dg_device_arch(char *buf, size_t size) {
+    if (!buf || size == 0) return fail(DG_EINVAL, "null buffer");
+    const std::string a = device_arch();
+    if (a.size() + 1 > size) return fail(DG_EINVAL, "buffer too small");
+    std::memcpy(buf, a.c_str(), a.size() + 1);
+    return DG_OK;
+}
+
+// File format: one entry per line, "arch P precision av waves stage_us",
+// '#' starts a comment line.
+int dg_tuning_save(const char *path, int *entries) {
+    if (!path) return fail(DG_EINVAL, "path is NULL");
+    std::ostringstream os;
+    os << "# arch P precision av waves_per_block stage_us\n";
+    int n = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_tune) {
+            char line[256];
+            std::snprintf(line, sizeof(line), "%s %d %d %d %d %.3f\n", std::get<0>(kv.first).c_str(),
+                          std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), kv.second.waves,
+                          kv.second.stage_us);
+            os << line;
+            ++n;
+        }
+    }
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return fail(DG_EINVAL, std::string("cannot open ") + path + " for writing");
+    f << os.str();
+    if (!f) return fail(DG_EINVAL, std::string("write to ") + path + " failed");
+    if (entries) *entries = n;
+    return DG_OK;
+}
+
+int dg_tuning_load(const char *path, int *entries) {
+    if (!path) return fail(DG_EINVAL, "path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(DG_EINVAL, std::string("cannot open ") + path);
+    std::vector<std::pair<TuneKey, TuneEntry>> got;
+    std::string line;
+    int lineno = 0;
+    while (std::getline(f, line)) {
+        ++lineno;
+        const size_t b = line.find_first_not_of(" \t\r");
+        if (b == std::string::npos || line[b] == '#') continue;
+        std::istringstream is(line);
+        std::string arch, extra;
+        int P = 0, prec = -1, av = -1, w = 0;
+        double us = 0.0;
+        if (!(is >> arch >> P >> prec >> av >> w >> us) || (is >> extra) || P < 1 || P > 5 ||
+            (prec != DG_FP32 && prec != DG_FP32_BF16X3) || (av != 0 && av != 1) || !tunable_waves(w))
+            return fail(DG_EINVAL, std::string(path) + ":" + std::to_string(lineno) + ": bad tuning entry");
+        got.emplace_back(TuneKey(arch, P, prec, av), TuneEntry{w, us});
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    if (entries) *entries = int(got.size());
     return DG_OK;
 }
 
@@ -1025,15 +1165,18 @@ struct Group {
     int P = 0;
     bool bf3 = false;
     bool av = false;               // viscous handles: sensor and gradient records too
+    int waves = 4;                 // stage kernel workgroup shape (tuning table or default)
     std::vector<int> slots;
     void *jobs = nullptr;          // [2][5][max_slots] stage records
     void *avjobs = nullptr;        // [2][5][max_slots] sensor/gradient records
-    void *items = nullptr;
+    void *items = nullptr;         // (job, tile) of the stage kernel
     size_t items_cap = 0;          // entries (int2)
     void *eitems = nullptr;        // viscous: (job, block of 256 elements) for the per-element sensor
     size_t eitems_cap = 0;
-    int *counts = nullptr;         // device [2]: items, eitems
-    int nitems = 0, neitems = 0;
+    void *aitems = nullptr;        // viscous: (job, tile) of the gradient and per-node sensor
+    size_t aitems_cap = 0;
+    int *counts = nullptr;         // device [3]: items, eitems, aitems
+    int nitems = 0, neitems = 0, naitems = 0;
 };
 
 }  // namespace
@@ -1059,6 +1202,7 @@ struct dg_batch {
             if (g.avjobs) (void)hipFree(g.avjobs);
             if (g.items) (void)hipFree(g.items);
             if (g.eitems) (void)hipFree(g.eitems);
+            if (g.aitems) (void)hipFree(g.aitems);
             if (g.counts) (void)hipFree(g.counts);
         }
     }
@@ -1094,9 +1238,13 @@ int rebuild(dg_batch *b, hipStream_t st) {
             ng.P = P;
             ng.bf3 = bf3;
             ng.av = av;
+            // the shape the tuning table holds for this kind now; the group
+            // keeps it for its lifetime
+            const int tw = tuned_waves(device_arch(), P, bf3 ? DG_FP32_BF16X3 : DG_FP32, av);
+            ng.waves = tw ? tw : mfma_default_waves();
             if (hipMalloc(&ng.jobs, 2 * 5 * max_jobs * mfma_args_bytes()) != hipSuccess ||
                 (av && hipMalloc(&ng.avjobs, 2 * 5 * max_jobs * av_args_bytes()) != hipSuccess) ||
-                hipMalloc(reinterpret_cast<void **>(&ng.counts), 2 * sizeof(int)) != hipSuccess) {
+                hipMalloc(reinterpret_cast<void **>(&ng.counts), 3 * sizeof(int)) != hipSuccess) {
                 if (ng.jobs) (void)hipFree(ng.jobs);
                 if (ng.avjobs) (void)hipFree(ng.avjobs);
                 return fail(DG_ENOMEM, "batch table allocation failed");
@@ -1115,7 +1263,7 @@ int rebuild(dg_batch *b, hipStream_t st) {
         const size_t nj = g.slots.size();
         const size_t rec = mfma_args_bytes(), arec = av_args_bytes();
         std::vector<char> jobs(2 * 5 * max_jobs * rec, 0), avjobs(g.av ? 2 * 5 * max_jobs * arec : 0, 0);
-        std::vector<int> items, eitems;
+        std::vector<int> items, eitems, aitems;
         for (size_t j = 0; j < nj; ++j) {
             Slot &s = b->slots[g.slots[j]];
             dg_mesh *m = s.mesh;
@@ -1141,14 +1289,14 @@ int rebuild(dg_batch *b, hipStream_t st) {
                         ms.cfl_accum = 1;
                         ms.vmax_out = vout;
                     }
-                    mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms,
+                    mfma_fill_args(m->dm, in[st5], out[st5], R, st5, ms, g.waves,
                                    jobs.data() + ((ps * 5 + st5) * max_jobs + j) * rec, eps, Q);
                     if (g.av)
                         av_fill_args(m->dm, in[st5], eps, Q, st5 == 0 ? vin : nullptr,
                                      avjobs.data() + ((ps * 5 + st5) * max_jobs + j) * arec);
                 }
             }
-            const int nt = mfma_tiles(m->dm);
+            const int nt = mfma_tiles(m->dm, g.waves);
             for (int tt = 0; tt < nt; ++tt) {
                 items.push_back(int(j));
                 items.push_back(tt);
@@ -1159,10 +1307,16 @@ int rebuild(dg_batch *b, hipStream_t st) {
                     eitems.push_back(int(j));
                     eitems.push_back(tt);
                 }
+                const int na = av_tiles(m->dm);
+                for (int tt = 0; tt < na; ++tt) {
+                    aitems.push_back(int(j));
+                    aitems.push_back(tt);
+                }
             }
         }
         g.nitems = int(items.size() / 2);
         g.neitems = int(eitems.size() / 2);
+        g.naitems = int(aitems.size() / 2);
         // work lists grow by doubling; a new table means a new address, so
         // the captured graph is stale
         auto grow = [&](void **p, size_t *cap, size_t need) -> int {
@@ -1178,15 +1332,19 @@ int rebuild(dg_batch *b, hipStream_t st) {
             return DG_OK;
         };
         if (int rc = grow(&g.items, &g.items_cap, size_t(g.nitems))) return rc;
-        if (g.av)
+        if (g.av) {
             if (int rc = grow(&g.eitems, &g.eitems_cap, size_t(g.neitems))) return rc;
+            if (int rc = grow(&g.aitems, &g.aitems_cap, size_t(g.naitems))) return rc;
+        }
         HIP_TRY(hipMemcpyAsync(g.jobs, jobs.data(), jobs.size(), hipMemcpyHostToDevice, st));
         if (g.av) HIP_TRY(hipMemcpyAsync(g.avjobs, avjobs.data(), avjobs.size(), hipMemcpyHostToDevice, st));
         if (!items.empty())
             HIP_TRY(hipMemcpyAsync(g.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, st));
         if (!eitems.empty())
             HIP_TRY(hipMemcpyAsync(g.eitems, eitems.data(), eitems.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        const int counts[2] = {g.nitems, g.neitems};
+        if (!aitems.empty())
+            HIP_TRY(hipMemcpyAsync(g.aitems, aitems.data(), aitems.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        const int counts[3] = {g.nitems, g.neitems, g.naitems};
         HIP_TRY(hipMemcpyAsync(g.counts, counts, sizeof(counts), hipMemcpyHostToDevice, st));
         // the host buffers go out of scope: wait for the copies
         HIP_TRY(hipStreamSynchronize(st));
@@ -1214,10 +1372,12 @@ int batch_step(dg_batch *b, int ps, hipStream_t st) {
         for (const Group &g : b->groups) {
             if (g.av) {
                 const char *avjobs = static_cast<const char *>(g.avjobs) + (ps * 5 + s5) * nj * arec;
-                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.items, g.counts, g.eitems, g.counts + 1, st));
+                HIP_TRY(launch_av_batch(g.P, s5 == 0, avjobs, g.aitems, g.counts + 2, int(g.aitems_cap), g.eitems,
+                                        g.counts + 1, int(g.eitems_cap), st));
             }
             const char *jobs = static_cast<const char *>(g.jobs) + (ps * 5 + s5) * nj * rec;
-            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, jobs, g.items, g.counts, st));
+            HIP_TRY(launch_stage_mfma_batch(g.P, g.bf3, g.av, g.waves, jobs, g.items, g.counts, int(g.items_cap),
+                                            st));
         }
     for (int i : b->singles) {
         Slot &s = b->slots[i];

@@ -361,7 +361,9 @@ template <typename T, int P>
 __device__ __forceinline__ void sensor_elem_body(const AvArgs<T> &a, const int tile) {
     using O = Order<P>;
     constexpr int Np = O::Np, Nfp = O::Nfp;
-    constexpr int NR = Np + 1;   // padded rows spread the threads over the LDS banks
+    // an odd row stride puts the threads' rows in distinct LDS banks (Np is
+    // even for P = 2, 3 and odd otherwise)
+    constexpr int NR = Np | 1;
     __shared__ T sVi[Np * Np];
     __shared__ T sR[kBlock * NR];
     LdsCopy<T, Np * Np> vic;
@@ -511,18 +513,17 @@ __global__ __launch_bounds__(kBlock) void k_avgrad(AvArgs<T> a) {
 
 // Batched meshes of one order (FP32 viscous handles): work item = (job,
 // tile), a job being one mesh's argument record for this stage.
-// All three are persistent over their work list, whose length they read
-// from device memory (a captured launch stays valid when the list changes).
+// One work item per block; the grid covers the list's capacity and the
+// length is read from device memory (a captured launch stays valid when the
+// list changes); surplus blocks exit.
 template <int P, bool CFL>
 __global__ __launch_bounds__(kBlock) void k_sensor_batch(const AvArgs<float> *__restrict__ jobs,
                                                          const int2 *__restrict__ items,
                                                          const int *__restrict__ nitems_dev) {
-    const int n = *nitems_dev;
-    for (int w = blockIdx.x; w < n; w += gridDim.x) {
-        const int2 it = items[w];
-        sensor_body<float, P, CFL>(jobs[it.x], it.y);
-        __syncthreads();
-    }
+    const int w = int(blockIdx.x);
+    if (w >= *nitems_dev) return;
+    const int2 it = items[w];
+    sensor_body<float, P, CFL>(jobs[it.x], it.y);
 }
 
 // Batched per-element sensor: work item = (job, block of kBlock elements).
@@ -530,24 +531,20 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_sensor_elem_batch(const AvArgs<float> *__restrict__ jobs,
                                                               const int2 *__restrict__ items,
                                                               const int *__restrict__ nitems_dev) {
-    const int n = *nitems_dev;
-    for (int w = blockIdx.x; w < n; w += gridDim.x) {
-        const int2 it = items[w];
-        sensor_elem_body<float, P>(jobs[it.x], it.y);
-        __syncthreads();
-    }
+    const int w = int(blockIdx.x);
+    if (w >= *nitems_dev) return;
+    const int2 it = items[w];
+    sensor_elem_body<float, P>(jobs[it.x], it.y);
 }
 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_avgrad_batch(const AvArgs<float> *__restrict__ jobs,
                                                          const int2 *__restrict__ items,
                                                          const int *__restrict__ nitems_dev) {
-    const int n = *nitems_dev;
-    for (int w = blockIdx.x; w < n; w += gridDim.x) {
-        const int2 it = items[w];
-        avgrad_body<float, P>(jobs[it.x], it.y);
-        __syncthreads();
-    }
+    const int w = int(blockIdx.x);
+    if (w >= *nitems_dev) return;
+    const int2 it = items[w];
+    avgrad_body<float, P>(jobs[it.x], it.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,23 +1081,25 @@ void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned 
 
 int sensor_elem_blocks(const DevMesh &m) { return (m.K + kBlock - 1) / kBlock; }
 
+int av_tiles(const DevMesh &m) { return nblocks_rt(m.K, m.P); }
+
 hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, const int *nitems_dev,
-                           const void *eitems, const int *neitems_dev, hipStream_t st) {
+                           int capacity, const void *eitems, const int *neitems_dev, int ecapacity,
+                           hipStream_t st) {
+    if (capacity <= 0) return hipSuccess;
     const auto *j = static_cast<const AvArgs<float> *>(jobs);
     const auto *it = static_cast<const int2 *>(items);
     const auto *eit = static_cast<const int2 *>(eitems);
     return with_order(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
-        static const int gs = resident_grid(k_sensor_batch<PP, true>, kBlock);
-        static const int ge = resident_grid(k_sensor_elem_batch<PP>, kBlock);
-        static const int gg = resident_grid(k_avgrad_batch<PP>, kBlock);
         if (cfl)
-            hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(gs), dim3(kBlock), 0, st, j, it, nitems_dev);
-        else
-            hipLaunchKernelGGL((k_sensor_elem_batch<PP>), dim3(ge), dim3(kBlock), 0, st, j, eit, neitems_dev);
+            hipLaunchKernelGGL((k_sensor_batch<PP, true>), dim3(capacity), dim3(kBlock), 0, st, j, it, nitems_dev);
+        else if (ecapacity > 0)
+            hipLaunchKernelGGL((k_sensor_elem_batch<PP>), dim3(ecapacity), dim3(kBlock), 0, st, j, eit,
+                               neitems_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(gg), dim3(kBlock), 0, st, j, it, nitems_dev);
+        hipLaunchKernelGGL((k_avgrad_batch<PP>), dim3(capacity), dim3(kBlock), 0, st, j, it, nitems_dev);
         return hipGetLastError();
     });
 }

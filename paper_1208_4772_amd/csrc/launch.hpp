@@ -113,27 +113,15 @@ int mfma_curved_bit();
 // work list of (record, tile) items, all meshes of order P
 size_t mfma_args_bytes();
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
-                    void *out, const void *eps = nullptr, const void *Q = nullptr);
-int mfma_tiles(const DevMesh &m);
-// Batched launches are persistent: a grid of as many workgroups as the
-// device holds resident at once (compute units x resident blocks per CU of
-// that kernel, a multiple of the 8 XCDs) walks a work list whose length
-// the kernels read from device memory, so that a captured launch stays
-// valid when solves join or leave; every block is resident, so the static
-// split of the list keeps the blocks balanced.
-template <typename K>
-int resident_grid(K kernel, int block_threads) {
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-        ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block_threads, 0) != hipSuccess || per <= 0)
-        per = 1;
-    const int g = ncu * per / 8 * 8;
-    return g < 8 ? 8 : g;
-}
-hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items,
-                                   const int *nitems_dev, hipStream_t st);
+                    int waves, void *out, const void *eps = nullptr, const void *Q = nullptr);
+int mfma_tiles(const DevMesh &m, int waves);
+int mfma_default_waves();
+// Batched launches: one work item per workgroup over a list whose length
+// the kernels read from device memory (nitems_dev) and whose capacity sets
+// the grid, so that a captured launch stays valid while solves join or
+// leave; a list that outgrows its capacity needs a new capture.
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, int waves, const void *jobs, const void *items,
+                                   const int *nitems_dev, int capacity, hipStream_t st);
 // CFL bound of state U (FP64) into the kVmaxSlots slots at *slot as bit
 // patterns (the maximum over them is the bound); raises *flag on bad states.
 // FP32 handles take the matrix-core kernel's own per-node bound
@@ -169,11 +157,14 @@ hipError_t launch_avgrad(const DevMesh &m, const void *U, const void *eps, void 
 // gradient over all of them
 size_t av_args_bytes();
 void av_fill_args(const DevMesh &m, const void *U, void *eps, void *Q, unsigned long long *vmax, void *out);
-// items: (job, tile) pairs of the stage kernel's tiles; eitems: (job, block)
-// pairs of blocks of 256 elements for the per-element sensor
+// items: (job, tile) pairs of the viscous kernels' tiles (av_tiles per
+// mesh); eitems: (job, block) pairs of blocks of 256 elements for the
+// per-element sensor
 hipError_t launch_av_batch(int P, bool cfl, const void *jobs, const void *items, const int *nitems_dev,
-                           const void *eitems, const int *neitems_dev, hipStream_t st);
+                           int capacity, const void *eitems, const int *neitems_dev, int ecapacity,
+                           hipStream_t st);
 int sensor_elem_blocks(const DevMesh &m);
+int av_tiles(const DevMesh &m);
 // CFL reduction -> scal[S_DT] (dt_fixed > 0 overrides), accumulates S_T,
 // S_DTMIN/MAX, S_STEPS; raises *flag on bad states.
 hipError_t launch_cfl(const DevMesh &m, const void *U, const void *eps, double dt_fixed,

@@ -665,17 +665,19 @@ template <int P, bool BF3, int W, bool AV>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(waves_per_simd<P, BF3, W, AV>())))
 void k_stage_mfma_batch(const MfmaArgs *__restrict__ jobs, const int2 *__restrict__ items,
                         const int *__restrict__ nitems_dev) {
-    // persistent over the work list, whose length is read from device
-    // memory (a captured launch stays valid when the list changes); each
-    // XCD (block b runs on XCD b % 8) sweeps a contiguous eighth of it
+    // one work item per workgroup; the grid covers the list's capacity and
+    // the length is read from device memory, so a captured launch stays
+    // valid while the list changes.  XCD x (block b runs on XCD b % 8) takes
+    // the x-th contiguous eighth of the items present; surplus blocks exit.
+    // (A loop over several items per workgroup raised the register count
+    // enough to spill: every value derived from the thread index was hoisted
+    // out of it.)
     const int n = *nitems_dev;
-    const int per = (n + 7) / 8, x = blockIdx.x % 8, stride = gridDim.x / 8;
-    const int end = min(n, (x + 1) * per);
-    for (int w = x * per + int(blockIdx.x / 8); w < end; w += stride) {
-        const int2 it = items[w];
-        stage_tile<P, BF3, W, AV>(jobs[it.x], it.y);
-        __syncthreads();   // the next item reuses the LDS
-    }
+    const int per = (n + 7) / 8, i = int(blockIdx.x / 8);
+    const int w = int(blockIdx.x % 8) * per + i;
+    if (i >= per || w >= n) return;
+    const int2 it = items[w];
+    stage_tile<P, BF3, W, AV>(jobs[it.x], it.y);
 }
 
 template <int P>
@@ -808,6 +810,8 @@ int mfma_elements_per_block(int P, int waves) {
 
 int mfma_curved_bit() { return kCurvedBit; }
 
+int mfma_default_waves() { return kWaves; }
+
 static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                           const MfmaStep &step, int waves, const void *eps = nullptr,
                           const void *Q = nullptr) {
@@ -850,39 +854,42 @@ static MfmaArgs make_args(const DevMesh &m, const void *Uin, void *Uout, void *R
 
 size_t mfma_args_bytes() { return sizeof(MfmaArgs); }
 
-// Batches use the default workgroup shape of their order.
+// A batch group runs one workgroup shape (waves per workgroup) for all its
+// meshes: records and tiles are made with the group's shape.
 void mfma_fill_args(const DevMesh &m, const void *Uin, void *Uout, void *R, int stage, const MfmaStep &step,
-                    void *out, const void *eps, const void *Q) {
-    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, default_waves(m.P), eps, Q);
+                    int waves, void *out, const void *eps, const void *Q) {
+    const MfmaArgs a = make_args(m, Uin, Uout, R, nullptr, stage, step, waves, eps, Q);
     std::memcpy(out, &a, sizeof(a));
 }
 
-int mfma_tiles(const DevMesh &m) {
-    const int eb = mfma_elements_per_block(m.P, default_waves(m.P));
+int mfma_tiles(const DevMesh &m, int waves) {
+    const int eb = mfma_elements_per_block(m.P, waves);
     return (m.K + eb - 1) / eb;
 }
 
-hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, const void *jobs, const void *items,
-                                   const int *nitems_dev, hipStream_t st) {
+hipError_t launch_stage_mfma_batch(int P, bool bf3, bool av, int waves, const void *jobs, const void *items,
+                                   const int *nitems_dev, int capacity, hipStream_t st) {
+    if (capacity <= 0) return hipSuccess;
     const auto *j = static_cast<const MfmaArgs *>(jobs);
     const auto *it = static_cast<const int2 *>(items);
     return with_order_m(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
-        constexpr int W = default_waves(PP);
-        const dim3 block(64 * W);
-        auto go = [&](auto kern) {
-            static const int g = resident_grid(kern, 64 * W);
-            hipLaunchKernelGGL(kern, dim3(g), block, 0, st, j, it, nitems_dev);
-        };
-        if (bf3 && av)
-            go(k_stage_mfma_batch<PP, true, W, true>);
-        else if (bf3)
-            go(k_stage_mfma_batch<PP, true, W, false>);
-        else if (av)
-            go(k_stage_mfma_batch<PP, false, W, true>);
-        else
-            go(k_stage_mfma_batch<PP, false, W, false>);
-        return hipGetLastError();
+        return with_waves(waves, [&](auto WC) {
+            constexpr int W = decltype(WC)::value;
+            const dim3 grid(unsigned((capacity + 7) / 8 * 8)), block(64 * W);
+            if (bf3 && av)
+                hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, true>), grid, block, 0, st, j, it, nitems_dev);
+            else if (bf3)
+                hipLaunchKernelGGL((k_stage_mfma_batch<PP, true, W, false>), grid, block, 0, st, j, it,
+                                   nitems_dev);
+            else if (av)
+                hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, true>), grid, block, 0, st, j, it,
+                                   nitems_dev);
+            else
+                hipLaunchKernelGGL((k_stage_mfma_batch<PP, false, W, false>), grid, block, 0, st, j, it,
+                                   nitems_dev);
+            return hipGetLastError();
+        });
     });
 }
 

@@ -35,7 +35,8 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_estimate_footprint", "dg_batch_create", "dg_batch_destroy", "dg_batch_admit",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
            "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong", "dg_weak_operators",
-           "dg_batch_info")
+           "dg_batch_info", "dg_tuning_set", "dg_tuning_lookup", "dg_tuning_clear", "dg_tuning_save",
+           "dg_tuning_load", "dg_device_arch")
 
 
 class DGError(RuntimeError):
@@ -110,6 +111,13 @@ def lib():
         L.dg_batch_info.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
         L.dg_kernel_time.argtypes = [vp, vp, C.POINTER(d), C.POINTER(C.c_long)]
         L.dg_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(i), C.POINTER(d)]
+        cp = C.c_char_p
+        L.dg_tuning_set.argtypes = [cp, i, i, i, i]
+        L.dg_tuning_lookup.argtypes = [cp, i, i, i, C.POINTER(i)]
+        L.dg_tuning_clear.argtypes = []
+        L.dg_tuning_save.argtypes = [cp, C.POINTER(i)]
+        L.dg_tuning_load.argtypes = [cp, C.POINTER(i)]
+        L.dg_device_arch.argtypes = [C.c_char_p, sz]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or i
         _lib = L
@@ -343,8 +351,9 @@ class Solver:
 
     def autotune(self, U, stream=None):
         """Pick the stage kernel's workgroup shape (2, 4 or 8 wavefronts) by
-        timing (matrix-core path only); returns (waves_per_block, us per
-        launch)."""
+        timing (matrix-core path only), or take the tuning table's entry for
+        this kind of handle (then the time is 0); returns (waves_per_block,
+        us per launch)."""
         self._check_state(U)
         b, us = C.c_int(0), C.c_double(0.0)
         _check(lib().dg_autotune(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(self.work.data_ptr()),
@@ -375,6 +384,43 @@ class Solver:
         b = C.c_size_t()
         _check(lib().dg_mesh_footprint(self._h, C.byref(b)))
         return b.value
+
+
+class Tuning:
+    """The process-wide tuning table of workgroup shapes (``dg_tuning_*``)."""
+
+    @staticmethod
+    def set(arch, P, precision, av, waves):
+        _check(lib().dg_tuning_set(arch.encode(), int(P), PRECISIONS[precision], 1 if av else 0, int(waves)))
+
+    @staticmethod
+    def lookup(arch, P, precision, av):
+        w = C.c_int(0)
+        _check(lib().dg_tuning_lookup(arch.encode(), int(P), PRECISIONS[precision], 1 if av else 0,
+                                      C.byref(w)))
+        return w.value
+
+    @staticmethod
+    def clear():
+        _check(lib().dg_tuning_clear())
+
+    @staticmethod
+    def save(path):
+        n = C.c_int(0)
+        _check(lib().dg_tuning_save(str(path).encode(), C.byref(n)))
+        return n.value
+
+    @staticmethod
+    def load(path):
+        n = C.c_int(0)
+        _check(lib().dg_tuning_load(str(path).encode(), C.byref(n)))
+        return n.value
+
+    @staticmethod
+    def device_arch():
+        buf = C.create_string_buffer(64)
+        _check(lib().dg_device_arch(buf, 64))
+        return buf.value.decode()
 
 
 def estimate_footprint(K, P, precision="fp32", av=False):

@@ -151,6 +151,27 @@ class Server:
         if self.verbose:
             print(msg, flush=True)
 
+    def tune(self, requests):
+        """Workgroup shape per kind of solve in the mix (order, viscosity) at
+        the server's precision: dg_autotune on the request of median size of
+        each kind, unless the tuning table already holds it.  Batch groups
+        created afterwards take these shapes.  Returns {(P, av): waves}."""
+        if self.precision == "fp64":
+            return {}
+        kinds = {}
+        for r in requests:
+            kinds.setdefault((r.P, bool(r.av)), []).append(r)
+        shapes = {}
+        for (P, av), rs in sorted(kinds.items()):
+            rs = sorted(rs, key=lambda r: r.case.K)
+            req = rs[len(rs) // 2]
+            sol = dg.Solver.from_case(req.case, self.precision, device=self.device)
+            try:
+                shapes[(P, av)] = sol.autotune(sol.state(req.case.U0))[0]
+            finally:
+                sol.close()
+        return shapes
+
     def run(self, requests):
         import torch
         batch = dg.Batch(self.budget, self.max_slots)
@@ -237,13 +258,29 @@ def main(argv=None):
     ap.add_argument("--max-slots", type=int, default=16)
     ap.add_argument("--chunk-steps", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--no-tune", action="store_true", help="batch groups keep the default workgroup shape")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="tuning table file: loaded if it exists, written after tuning")
     a = ap.parse_args(argv)
     t = time.perf_counter()
     reqs = make_requests(a.requests, a.mean_gap, a.seed)
     print(f"built {len(reqs)} requests in {time.perf_counter() - t:.1f} s", flush=True)
     srv = Server(int(a.budget_gib * 2**30), a.max_slots, a.precision, a.chunk_steps, verbose=True)
+    shapes = {}
+    if not a.no_tune:
+        import os
+        if a.tuning_cache and os.path.exists(a.tuning_cache):
+            dg.Tuning.load(a.tuning_cache)
+        t = time.perf_counter()
+        shapes = srv.tune(reqs)
+        print(f"tuned {len(shapes)} kinds in {time.perf_counter() - t:.1f} s: "
+              + ", ".join(f"P={P}{' av' if av else ''}: {w}" for (P, av), w in shapes.items()), flush=True)
+        if a.tuning_cache:
+            dg.Tuning.save(a.tuning_cache)
     rep = srv.run(reqs)
-    print(json.dumps(rep.summary()), flush=True)
+    summ = rep.summary()
+    summ["workgroup_waves"] = {f"P{P}{'_av' if av else ''}": w for (P, av), w in shapes.items()}
+    print(json.dumps(summ), flush=True)
 
 
 if __name__ == "__main__":

@@ -86,3 +86,25 @@ def test_state_errors():
     e = accuracy.state_errors(b, a)
     assert e["max_abs"] == 0.5
     assert abs(e["rel_l2"] - 0.5 / math.sqrt(a.size)) < 1e-15
+
+
+def test_shock_position_is_the_last_rise_through_critical_cp():
+    """Upper-surface C_p = C_p* + 2 (x - 0.6) with a wiggle through C_p*
+    near the leading edge: the shock is the crossing at x = 0.6 (linear
+    between nodes, so exact); no crossing gives NaN."""
+    r, s = dg.reference_nodes(3)
+    case = meshgen.make_case("airfoil", r, s, scale=0.01, P=3)
+    geo = accuracy.Geometry(case)
+    q = case.freestream
+    g = 1.4
+    rho0, u0, v0 = q[0], q[1] / q[0], q[2] / q[0]
+    p0 = (g - 1) * (q[3] - 0.5 * rho0 * (u0 * u0 + v0 * v0))
+    qd = 0.5 * rho0 * (u0 * u0 + v0 * v0)
+    cstar = accuracy.critical_cp(0.8)
+    x = case.x
+    cp = np.where(x < 0.15, cstar + (x - 0.1),
+                  np.where(x < 0.2, cstar + 0.05 - 2.0 * (x - 0.15), cstar + 2.0 * (x - 0.6)))
+    U = np.stack([np.ones_like(x), 0 * x, 0 * x, (p0 + qd * cp) / (g - 1)], 1)
+    assert geo.wall_loads(U, q)["shock_x"] == pytest.approx(0.6, abs=1e-9)
+    U[:, 3] = (p0 + qd * (cstar + 0.1)) / (g - 1)
+    assert math.isnan(geo.wall_loads(U, q)["shock_x"])

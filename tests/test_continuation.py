@@ -65,3 +65,14 @@ def test_failed_state_check_stops_the_continuation():
 def test_orders_must_increase():
     with pytest.raises(ValueError):
         continuation.run(lambda P: FakeSolver(P), None, (3, 2))
+
+
+def test_fixed_iterations_per_order():
+    """The paper's way: the lower orders run a fixed number of iterations
+    (switch residual 0), the last until the final residual."""
+    r = continuation.run(lambda P: FakeSolver(P), None, (2, 3, 4), check_every=100,
+                         switch_residual={2: 0.0, 3: 0.0, 4: 0.0}, final_residual=1e-4,
+                         max_steps_per_order={2: 300, 3: 200, 4: 10000})
+    assert [leg.steps for leg in r.legs] == [300, 200, 400]
+    assert [leg.reason for leg in r.legs] == ["step limit", "step limit", "converged"]
+    assert r.converged

@@ -309,7 +309,8 @@ def test_critical_pressure_coefficient_is_sonic():
 def test_shock_position_is_the_upward_crossing():
     """A wall pressure with C_p = C_p* + 2 (x - 0.6) on the upper surface
     crosses C_p* upwards at x = 0.6 exactly (the interpolation is linear in
-    x); a pressure that stays above C_p* has no shock."""
+    x); a pressure that stays above C_p* has no shock; with an earlier
+    crossing near the leading edge the shock is still the last one."""
     P = 3
     R = ref(P)
     m = meshgen.naca4_ogrid(60, 6, jitter=0.0)
@@ -328,6 +329,15 @@ def test_shock_position_is_the_upward_crossing():
     p = p0 + qdyn * (cstar + 0.1 + 0 * x)
     U[:, 3] = p / (G - 1)
     assert math.isnan(dgn.shock_position(o, U, q, M))
+    # a wiggle near the leading edge (up through C_p* at x = 0.1, down at
+    # 0.2) before the shock at 0.6: the shock is the last upward crossing
+    cp = np.where(x < 0.15, cstar + (x - 0.1),
+                  np.where(x < 0.2, cstar + 0.05 - 2.0 * (x - 0.15), cstar + 2.0 * (x - 0.6)))
+    U[:, 3] = (p0 + qdyn * cp) / (G - 1)
+    xs, cs = dgn.upper_surface_cp(o, U, q)
+    rising = [i for i in range(xs.size - 1) if cs[i] < cstar <= cs[i + 1]]
+    assert len(rising) >= 2
+    assert dgn.shock_position(o, U, q, M) == pytest.approx(0.6, abs=1e-9)
 
 
 # -- node family: blending exponents (R3) -------------------------------------
