@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import json
 import math
+import sys
 
 import numpy as np
 
@@ -187,6 +188,10 @@ def run_stations(case, precision, stations, device="cuda:0"):
         done = n
         out.append(dict(step=n, status=st.status, t=st.t if not out else out[-1]["t"] + st.t,
                         U=U.double().cpu().numpy()))
+        if case.av and st.status == 0:
+            out[-1]["viscous_elements"] = int((sol.viscosity(U) > 0).sum().item())
+        print(f"[{case.name} {precision}] step {n} t {out[-1]['t']:.5f} status {st.status}",
+              file=sys.stderr, flush=True)
         if st.status != 0:
             break
     sol.close()
@@ -203,6 +208,8 @@ def precision_report(case, stations, precisions=("fp32", "bf16x3"), loads=True):
     for i, r64 in enumerate(ref):
         row = dict(step=r64["step"], t=r64["t"], fp64=dict(
             status=r64["status"], entropy_error=geo.entropy_error(r64["U"], case.freestream)))
+        if "viscous_elements" in r64:
+            row["fp64"]["viscous_elements"] = r64["viscous_elements"]
         if loads:
             row["fp64"]["wall"] = geo.wall_loads(r64["U"], case.freestream)
         for p, rr in runs.items():
@@ -211,6 +218,8 @@ def precision_report(case, stations, precisions=("fp32", "bf16x3"), loads=True):
                 continue
             e = dict(status=rr[i]["status"], t=rr[i]["t"], **state_errors(rr[i]["U"], r64["U"]),
                      entropy_error=geo.entropy_error(rr[i]["U"], case.freestream))
+            if "viscous_elements" in rr[i]:
+                e["viscous_elements"] = rr[i]["viscous_elements"]
             if loads:
                 e["wall"] = geo.wall_loads(rr[i]["U"], case.freestream)
             row[p] = e
@@ -259,6 +268,8 @@ def main(argv=None):
     ap.add_argument("--stations", type=int, default=4)
     ap.add_argument("--start", default=None, choices=["freestream", "potential", "damped"],
                     help="initial state of the cylinder/airfoil (default: the case's own)")
+    ap.add_argument("--kappa", type=float, default=None, help="sensor half-width (default: the case's own)")
+    ap.add_argument("--precisions", default="fp32,bf16x3", help="reduced precisions compared with FP64")
     a = ap.parse_args(argv)
     if a.report == "roofline":
         res = freestream_and_conservation(a.scale, a.steps or 200)
@@ -267,9 +278,12 @@ def main(argv=None):
         r, s = dg.reference_nodes(P)
         case = meshgen.make_case(a.report, r, s, scale=a.scale,
                                  **({"start": a.start} if a.start else {}))
+        if a.kappa is not None:
+            case.av_kappa = a.kappa
         n = a.steps or case.steps
         stations = sorted({max(1, round(n * (i + 1) / a.stations)) for i in range(a.stations)})
-        res = precision_report(case, stations)
+        res = precision_report(case, stations, precisions=tuple(a.precisions.split(",")))
+        res["av_kappa"] = case.av_kappa
     print(json.dumps(_jsonable(res)), flush=True)
 
 

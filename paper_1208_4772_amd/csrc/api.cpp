@@ -3,6 +3,7 @@
 // preceded by the sensor and the viscous-gradient kernels).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -74,6 +75,9 @@ int tuned_waves(const std::string &arch, int P, int precision, int av) {
 
 struct dg_mesh {
     DevMesh dm;
+    // unique per handle over the process's life (an address can be reused
+    // by a later handle; this number is not)
+    unsigned long long serial = 0;
     int precision = DG_FP64_PLAIN;
     size_t elem_bytes = 8;
     std::vector<void *> allocs;
@@ -286,6 +290,10 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     dg_mesh *m = new dg_mesh();
+    {
+        static std::atomic<unsigned long long> next_serial{1};
+        m->serial = next_serial.fetch_add(1);
+    }
     DevMesh &dm = m->dm;
     dm.K = K;
     dm.P = P;
@@ -1186,7 +1194,12 @@ struct dg_batch {
     std::vector<Slot> slots;
     std::vector<Group> groups;
     std::vector<int> singles;      // slots stepped one by one (FP64 handles)
-    std::vector<int> prev_singles; // the set the captured graph holds
+    // what the captured graph's one-by-one launches were made for: slot,
+    // handle serial, state and work buffer of each (the handle's tables and
+    // the buffers' addresses are baked into the graph, so a new solve in a
+    // reused slot needs a new graph, even where the allocator hands out the
+    // same addresses again)
+    std::vector<std::tuple<int, unsigned long long, const void *, const void *>> graph_singles;
     bool dirty = true;
     long epoch_steps = 0;          // steps since the tables were last built
     hipStream_t cap_stream = nullptr;
@@ -1354,12 +1367,17 @@ int rebuild(dg_batch *b, hipStream_t st) {
         b->graph = nullptr;
     }
     // FP64 slots step inside the graph too, their launches carrying their
-    // buffers: a change of that set needs a new graph
-    if (b->singles != b->prev_singles && b->graph) {
+    // handles' and buffers' addresses: any change of those needs a new graph
+    std::vector<std::tuple<int, unsigned long long, const void *, const void *>> sig;
+    for (int i : b->singles) {
+        const Slot &s = b->slots[i];
+        sig.emplace_back(i, s.mesh->serial, s.U, s.work);
+    }
+    if (sig != b->graph_singles && b->graph) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
-    b->prev_singles = b->singles;
+    b->graph_singles = sig;
     b->epoch_steps = 0;
     b->dirty = false;
     return DG_OK;

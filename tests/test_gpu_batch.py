@@ -154,3 +154,39 @@ def test_joins_and_leaves_of_known_kinds_do_not_recapture():
     for req, Ub in results:
         Ua, _ = run_alone(*req)
         assert np.array_equal(Ua, Ub), req
+
+
+def test_reused_slot_with_fp64_handles_matches_alone():
+    """FP64 handles step one by one inside the batch's captured graph, whose
+    launches carry their handles' tables and buffers.  A solve finishes, its
+    handle is closed, and new solves take the same slot (one slot only; the
+    third has the second's shape, so the allocators may hand out the same
+    addresses again): each needs its own graph, and each result equals the
+    same solve run alone."""
+    import torch
+    reqs = [("cylinder", 3, 0.02, 6, "fp64", 0.4, True), ("airfoil", 2, 0.01, 7, "fp64", 0.7, True),
+            ("airfoil", 2, 0.01, 5, "fp64", 0.6, True)]
+    b = dg().Batch(1 << 34, 1)
+    for n, req in enumerate(reqs):
+        kind, P, scale, steps, prec, mach, av = req
+        print(f"[reuse fp64] request {n}: {req}", flush=True)
+        case, sol = make(kind, P, scale, prec, mach, av)
+        U = sol.state(case.U0)
+        assert b.admit(sol, U, steps) == 0
+        done = []
+        while not done:
+            assert b.advance(4) > 0
+            done = b.poll()
+        assert done == [0]
+        st = b.stats(0)
+        assert st.steps == steps and st.status == 0
+        torch.cuda.synchronize()
+        Ub = U.double().cpu().numpy()
+        b.release(0)
+        sol.close()
+        del U
+        Ua, sta = run_alone(*req)
+        assert np.array_equal(Ua, Ub), (req, np.abs(Ua - Ub).max())
+        assert sta.t == st.t
+        captures, _ = b.info()
+        assert captures == n + 1
