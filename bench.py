@@ -222,9 +222,12 @@ def serving_leg(budget_gib, precision="fp32"):
     reqs = serving.make_requests(64, 0.05, 64)
     build_s = time.perf_counter() - t0
     srv = serving.Server(int(budget_gib * 2 ** 30), 16, precision, 50)
+    # workgroup shapes per kind of solve in the mix, before the clock starts
+    shapes = srv.tune(reqs)
     rep = srv.run(reqs)
     out = rep.summary()
     out["build_s"] = round(build_s, 1)
+    out["workgroup_waves"] = {f"P{P}{'_av' if av else ''}": w for (P, av), w in shapes.items()}
     return out
 
 
@@ -367,6 +370,9 @@ def main():
     log(f"device copy: {gbs:.0f} GB/s; stage kernel at {achieved / gbs:.3f} of it")
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_budget_gib, args.precision)
+        # the batched aggregate beside the single-mesh rate of this run
+        out["serving"]["aggregate_over_single_mesh"] = round(
+            out["serving"]["aggregate_dof_updates_per_s"] / value, 4)
         log(f"serving: {out['serving']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
