@@ -105,13 +105,15 @@ def algorithmic_stage_bytes(case, s):
     return total, dict(curved=curved, interior_sides=interior_sides)
 
 
-def stage_kernel_label(case, precision, waves):
+def stage_kernel_label(case, precision, waves, form="nodal"):
     """The launch(es) one Runge-Kutta stage consists of: the stage kernel, and
     with artificial viscosity the sensor and gradient launches before it
     (their time is in the per-stage average, so their bytes are in the
     algorithmic figure; a step's first stage runs the sensor that also
     reduces the time-step bound, k_sensor, in place of k_sensor_elem)."""
     av = "true" if case.av else "false"
+    if form == "weak":
+        return f"k_stage_weak<{'double' if precision == 'fp64' else 'float'},{case.P}>"
     if precision == "fp64":
         k = f"k_stage<double,{case.P},{av}>"
     else:
@@ -238,6 +240,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="roofline", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--form", default="nodal", choices=["nodal", "weak"],
+                    help="discretisation: the nodal strong form or the over-integrated weak form")
+    ap.add_argument("--riemann", default="lf", choices=["lf", "hllc"], help="numerical flux")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -282,7 +287,7 @@ def main():
     final = {}
 
     def timed_run(precision, nsteps, warmup):
-        sol = dg.Solver.from_case(case, precision, device="cuda:0")
+        sol = dg.Solver.from_case(case, precision, device="cuda:0", form=args.form, riemann=args.riemann)
         U0 = sol.state(case.U0)
         U = U0.clone()
         if not args.no_autotune:
@@ -317,10 +322,13 @@ def main():
     sbytes = 8 if args.precision == "fp64" else 4
     launch_bytes, geo_info = algorithmic_stage_bytes(case, sbytes)
     achieved = launch_bytes / avg_s / 1e9
-    traffic = load_traffic(args.workload, args.precision, launch_bytes, case.av)
+    # counter traffic is committed for the default discretisation only
+    traffic = (load_traffic(args.workload, args.precision, launch_bytes, case.av)
+               if args.form == "nodal" and args.riemann == "lf" else None)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=stage_kernel_label(case, args.precision, tuned.get(args.precision, (0, 0.0))[0]),
+                    kernel=stage_kernel_label(case, args.precision, tuned.get(args.precision, (0, 0.0))[0],
+                                              args.form),
                     avg_launch_us=round(avg_s * 1e6, 3),
                     launches=5 * steps,
                     waves_per_block=tuned.get(args.precision, (0, 0.0))[0] or None,
@@ -342,8 +350,12 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "K": case.K, "P": case.P,
                    "dof": dofs, "precision": args.precision,
                    "curved_elements": geo_info["curved"]},
-        "roofline": roofline,
     }
+    if args.form != "nodal" or args.riemann != "lf":
+        # the byte model is the nodal one (the weak form moves the same state,
+        # register and traces; its straight-element geometry is smaller)
+        out["config"].update(form=args.form, riemann=args.riemann)
+    out["roofline"] = roofline
     if not args.no_fp64 and args.precision != "fp64":
         w64, st64, ok64 = timed_run("fp64", steps, args.warmup)
         out["fp64_plain"] = dict(value=dofs * 5 * steps / w64, ms_per_step=w64 * 1e3 / steps,

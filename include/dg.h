@@ -302,6 +302,17 @@ int dg_device_arch(char *buf, size_t size);
  * array and its work buffer: the unit of HBM-footprint admission. */
 int dg_mesh_footprint(const dg_mesh *mesh, size_t *bytes);
 
+/* Number of elements the handle treats as curved: those whose metric terms
+ * vary over the element beyond rounding (relative 1e-10 of the element's
+ * largest metric term) or whose face normals and Fscale vary along a face
+ * (Section 2, the isoparametric map; an affine element's map has constant
+ * metric terms).  Curved elements keep per-node (nodal form) or
+ * per-cubature-point (weak form) metric terms and, in the weak form, their
+ * own inverse mass matrix; the others use five to thirteen numbers.  -1 for
+ * FP64 nodal handles, whose stage kernel takes per-node metrics for every
+ * element.  Errors: DG_EINVAL. */
+int dg_mesh_curved(const dg_mesh *mesh, int *curved);
+
 /* Upper estimate of dg_mesh_footprint for a mesh not yet set up, so that a
  * server can decide admission before allocating anything. */
 int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *bytes);

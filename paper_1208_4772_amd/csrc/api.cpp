@@ -1131,6 +1131,12 @@ int dg_mesh_footprint(const dg_mesh *m, size_t *bytes) {
     return DG_OK;
 }
 
+int dg_mesh_curved(const dg_mesh *m, int *curved) {
+    if (!m || !curved) return fail(DG_EINVAL, "null argument");
+    *curved = m->dm.weak ? m->dm.wKc : (m->dm.fp32 ? m->dm.Kc : -1);
+    return DG_OK;
+}
+
 int dg_estimate_footprint(int K, int P, int precision, int av_enable, size_t *bytes) {
     if (!bytes || K < 1 || P < 1 || P > 5) return fail(DG_EINVAL, "bad arguments");
     const size_t Np = size_t(n_nodes(P)), Nfp = size_t(P + 1), k = size_t(K);

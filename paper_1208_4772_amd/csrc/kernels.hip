@@ -661,10 +661,14 @@ __global__ void k_affine_flags(int K, const double *__restrict__ geo, const doub
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
     bool affine = true;
+    // one scale for the four metric terms: a term that is near zero on this
+    // element (an edge nearly parallel to an axis) varies by the rounding of
+    // the others, which relative to itself can be large
+    double scale = 0;
+    for (int m = 0; m < 4; ++m)
+        for (int i = 0; i < Np; ++i) scale = fmax(scale, fabs(geo[(k * 4 + m) * Np + i]));
     for (int m = 0; m < 4; ++m) {
         const double *g = geo + (k * 4 + m) * Np;
-        double scale = 0;
-        for (int i = 0; i < Np; ++i) scale = fmax(scale, fabs(g[i]));
         for (int i = 1; i < Np; ++i) affine &= fabs(g[i] - g[0]) <= 1e-10 * scale;
     }
     for (int m = 0; m < 3; ++m) {

@@ -31,13 +31,20 @@ struct WShape {
     static constexpr int NQ = n * n, NG = n;
 };
 
-// elements per block: LDS of U, the cubature fluxes (2 x 4 x NQ), the face
-// fluxes (4 x 3 NG) and the right-hand side vector, within 60 KB
+// Elements per block: LDS of U, the cubature fluxes (2 x 4 x NQ), the face
+// fluxes (4 x 3 NG) and the right-hand side vector within a budget per
+// precision.  Measured at P = 5 on 1M elements: FP32 runs fastest with small
+// blocks (36 KB: 11 elements per block at P = 5, four blocks per CU), FP64
+// with large ones (60 KB: its registers, not the LDS, cap the resident
+// waves).  The reference operators stay in global memory (caches): staged
+// in LDS they cost more resident blocks than the reads they save.
+constexpr int kWeakBudgetF32 = 36 * 1024, kWeakBudgetF64 = 60 * 1024;
+
 template <typename T, int P>
 constexpr int weak_elems() {
     using S = WShape<P>;
     constexpr int per = (8 * S::Np + 8 * S::NQ + 12 * S::NG) * int(sizeof(T));
-    constexpr int e = (60 * 1024) / per;
+    constexpr int e = (sizeof(T) == 4 ? kWeakBudgetF32 : kWeakBudgetF64) / per;
     return e < 1 ? 1 : (e > 32 ? 32 : e);
 }
 
@@ -65,8 +72,6 @@ template <typename T, int P>
 __global__ __launch_bounds__(kWBlock) void k_stage_weak(WeakArgs<T> a) {
     using S = WShape<P>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NQ = S::NQ, NG = S::NG, EB = weak_elems<T, P>();
-    const T *Icub = a.ops, *Drc = Icub + NQ * Np, *Dsc = Drc + NQ * Np, *wq = Dsc + NQ * Np;
-    const T *If = wq + NQ, *Minv = If + NG * Nfp;
     __shared__ T sU[EB][kFields][Np];
     __shared__ T sA[EB][kFields][NQ];
     __shared__ T sB[EB][kFields][NQ];
@@ -75,6 +80,9 @@ __global__ __launch_bounds__(kWBlock) void k_stage_weak(WeakArgs<T> a) {
     const long k0 = (long)blockIdx.x * EB;
     const int nel = (int)min((long)EB, (long)a.K - k0);
     const int tid = threadIdx.x;
+
+    const T *Icub = a.ops, *Drc = Icub + NQ * Np, *Dsc = Drc + NQ * Np, *wq = Dsc + NQ * Np;
+    const T *If = wq + NQ, *Minv = If + NG * Nfp;
 
     for (int z = tid; z < nel * kFields * Np; z += kWBlock) (&sU[0][0][0])[z] = a.Uin[k0 * kFields * Np + z];
     __syncthreads();
@@ -150,45 +158,69 @@ __global__ __launch_bounds__(kWBlock) void k_stage_weak(WeakArgs<T> a) {
         for (int c = 0; c < kFields; ++c) sS[el][c][fg] = ws * (fm[c] - d[c]);
     }
     __syncthreads();
-    // V - S per node
+    // V - S per node, the four fields together (each operator entry read
+    // once for all of them)
     constexpr NodeFaceTable<P> kNF;
-    for (int z = tid; z < nel * kFields * Np; z += kWBlock) {
-        const int el = z / (kFields * Np), r = z - el * kFields * Np, c = r / Np, i = r - c * Np;
-        T b = 0;
-        for (int q = 0; q < NQ; ++q) b += Drc[q * Np + i] * sA[el][c][q] + Dsc[q * Np + i] * sB[el][c][q];
+    for (int z = tid; z < nel * Np; z += kWBlock) {
+        const int el = z / Np, i = z - el * Np;
+        T b[kFields] = {};
+        for (int q = 0; q < NQ; ++q) {
+            const T dr = Drc[q * Np + i], ds = Dsc[q * Np + i];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) b[c] += dr * sA[el][c][q] + ds * sB[el][c][q];
+        }
         const int nq = kNF.v[i];
         if (nq) {
             for (int t = 0; t < 2; ++t) {
                 const int e = t == 0 ? (nq & 255) - 1 : (nq >> 8) - 1;
                 if (e < 0) continue;
                 const int f = e / Nfp, j = e - f * Nfp;
-                for (int gq = 0; gq < NG; ++gq) b -= If[gq * Nfp + j] * sS[el][c][f * NG + gq];
+                for (int gq = 0; gq < NG; ++gq) {
+                    const T l = If[gq * Nfp + j];
+#pragma unroll
+                    for (int c = 0; c < kFields; ++c) b[c] -= l * sS[el][c][f * NG + gq];
+                }
             }
         }
-        sb[el][c][i] = b;
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) sb[el][c][i] = b[c];
     }
     __syncthreads();
-    // M_k^{-1} (V - S), then the Runge-Kutta update
+    // M_k^{-1} (V - S), then the Runge-Kutta update, the four fields of a
+    // node together
     const T dt = a.mode ? T(*a.dt) : T(0);
-    for (int z = tid; z < nel * kFields * Np; z += kWBlock) {
-        const int el = z / (kFields * Np), r = z - el * kFields * Np, c = r / Np, i = r - c * Np;
+    for (int z = tid; z < nel * Np; z += kWBlock) {
+        const int el = z / Np, i = z - el * Np;
         const long k = k0 + el;
         const int cs = a.widx[k];
-        T val = 0;
+        T val[kFields] = {};
         if (cs < 0) {
-            for (int j = 0; j < Np; ++j) val += Minv[i * Np + j] * sb[el][c][j];
-            val = val / a.geoA[k * 5 + 4];
+            for (int j = 0; j < Np; ++j) {
+                const T mij = Minv[i * Np + j];
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) val[c] += mij * sb[el][c][j];
+            }
+            const T J = a.geoA[k * 5 + 4];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) val[c] = val[c] / J;
         } else {
             const T *mk = a.minv + (long)cs * Np * Np + i * Np;
-            for (int j = 0; j < Np; ++j) val += mk[j] * sb[el][c][j];
+            for (int j = 0; j < Np; ++j) {
+                const T mij = mk[j];
+#pragma unroll
+                for (int c = 0; c < kFields; ++c) val[c] += mij * sb[el][c][j];
+            }
         }
-        const long idx = k0 * kFields * Np + z;
-        if (a.mode == 0) {
-            a.rhs[idx] = val;
-        } else {
-            const T rr = (a.stage == 0) ? dt * val : a.ra * a.R[idx] + dt * val;
-            a.R[idx] = rr;
-            a.Uout[idx] = sU[el][c][i] + a.rb * rr;
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) {
+            const long idx = k0 * kFields * Np + (el * kFields + c) * Np + i;
+            if (a.mode == 0) {
+                a.rhs[idx] = val[c];
+            } else {
+                const T rr = (a.stage == 0) ? dt * val[c] : a.ra * a.R[idx] + dt * val[c];
+                a.R[idx] = rr;
+                a.Uout[idx] = sU[el][c][i] + a.rb * rr;
+            }
         }
     }
 }

@@ -36,7 +36,7 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_batch_advance", "dg_batch_poll", "dg_batch_slot_stats", "dg_batch_release",
            "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong", "dg_weak_operators",
            "dg_batch_info", "dg_tuning_set", "dg_tuning_lookup", "dg_tuning_clear", "dg_tuning_save",
-           "dg_tuning_load", "dg_device_arch")
+           "dg_tuning_load", "dg_device_arch", "dg_mesh_curved")
 
 
 class DGError(RuntimeError):
@@ -118,6 +118,7 @@ def lib():
         L.dg_tuning_save.argtypes = [cp, C.POINTER(i)]
         L.dg_tuning_load.argtypes = [cp, C.POINTER(i)]
         L.dg_device_arch.argtypes = [C.c_char_p, sz]
+        L.dg_mesh_curved.argtypes = [vp, C.POINTER(i)]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or i
         _lib = L
@@ -379,6 +380,12 @@ class Solver:
 
     def dofs(self):
         return 4 * self.Np * self.K
+
+    def curved_elements(self):
+        """Elements the library treats as curved (-1: FP64 nodal handle)."""
+        n = C.c_int(0)
+        _check(lib().dg_mesh_curved(self._h, C.byref(n)))
+        return n.value
 
     def footprint(self):
         b = C.c_size_t()

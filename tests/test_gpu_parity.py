@@ -780,3 +780,33 @@ def test_weak_form_vortex_run_matches_oracle(precision):
     print(f"[weak vortex {precision}] rel L2 {err:.3e}")
     assert err <= RUN_TOL[precision]
     assert abs(st.t - info["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * info["t"]
+
+
+@pytest.mark.parametrize("form", ["nodal", "weak"])
+def test_curved_classification_matches_the_geometry(form):
+    """The library treats an element as curved exactly when its map is not
+    affine: none on the jittered straight meshes (whose edges nearly
+    parallel to an axis give near-zero metric terms, once mistaken for
+    varying ones), the wall elements of the cylinder and the airfoil, and
+    every element of the all-curved periodic mesh.  FP64 nodal handles take
+    per-node metrics everywhere and report -1."""
+    checks = [("roofline", 5, 0.02), ("vortex", 2, 1.0), ("cylinder", 4, 0.05), ("airfoil", 3, 0.01),
+              ("roofline_curved", 5, 0.005)]
+    for name, P, scale in checks:
+        R = ref(P)
+        case = meshgen.make_case(name, R.r, R.s, P=P, scale=scale)
+        m = case.mesh
+        if m.node_displacement is not None:
+            expect = case.K
+        elif m.curve is not None:
+            expect = int((m.bc == meshgen.BC_WALL).any(axis=1).sum())
+        else:
+            expect = 0
+        s = dg().Solver.from_case(case, "fp32", form=form, av=False)
+        got = s.curved_elements()
+        print(f"[curved {form}] {name} K={case.K}: library {got}, geometry {expect}", flush=True)
+        assert got == expect, (name, got, expect)
+        s.close()
+    R = ref(4)
+    case = meshgen.make_case("cylinder", R.r, R.s, P=4, scale=0.05)
+    assert dg().Solver.from_case(case, "fp64").curved_elements() == -1
