@@ -25,11 +25,12 @@ Readings (the paper gives the 3D operators by their definitions only):
 * nodes: the equispaced lattice (i, j, k) / P on the tetrahedron (the
   paper's 2D node family has no 3D table here; for the orders used, P <= 4,
   the lattice is well conditioned);
-* operators from their definitions with a monomial basis in
-  x = (1 + r)/2, y = (1 + s)/2, z = (1 + t)/2 (any polynomial basis gives the
-  same nodal operators): Dr = V_r V^-1, M = V^-T (exact monomial integrals)
-  V^-1, per face the 2D mass matrix of the face's Lagrange basis with
-  respect to a reference triangle of area 2, LIFT = M^-1 E;
+* operators from their definitions (any polynomial basis gives the same
+  nodal operators): Dr = V_r V^-1 with monomials in x = (1 + r)/2,
+  y = (1 + s)/2, z = (1 + t)/2; the mass matrix M = (V_o V_o^T)^-1 from a
+  basis orthonormal on the tetrahedron; per face the 2D mass matrix of the
+  face's Lagrange basis with respect to a reference triangle of area 2, the
+  same way from the orthonormal triangle basis; LIFT = M^-1 E;
 * sJ = physical face area / 2, J = physical volume / (4/3), Fscale = sJ / J;
 * slip wall: the mirror ghost state (normal momentum reversed);
 * time step: dt = CFL / max over face nodes of (P+1)^2 Fscale (|v| + c) / 2,
@@ -73,6 +74,36 @@ def monomials(P):
     return [(a, b, c) for a in range(P + 1) for b in range(P + 1 - a) for c in range(P + 1 - a - b)]
 
 
+def orthonormal_vandermonde2(P, r, s):
+    """Vandermonde matrix of the orthonormal modal basis of the triangle
+    (-1,-1), (1,-1), (-1,1) (the 2D oracle's basis)."""
+    from .refelem import basis
+    return np.stack([basis(r, s, i, j) for i in range(P + 1) for j in range(P + 1 - i)], 1)
+
+
+def orthonormal_vandermonde3(P, r, s, t):
+    """Vandermonde matrix of a basis orthonormal on the reference
+    tetrahedron: through the collapsed coordinates a = 2(1+r)/(-s-t) - 1,
+    b = 2(1+s)/(1-t) - 1, c = t,
+    psi_ijk = 2 sqrt2 p_i(a) p_j^(2i+1,0)(b) (1-b)^i p_k^(2i+2j+2,0)(c) (1-c)^(i+j)
+    with p^(alpha,beta) the Jacobi polynomials of unit norm (the product of
+    the collapse's Jacobian weights makes the modes orthonormal)."""
+    from .refelem import jacobi_normalized as jn
+    r, s, t = (np.asarray(v, dtype=np.float64) for v in (r, s, t))
+    st = -s - t
+    a = np.where(np.abs(st) > 1e-14, 2.0 * (1.0 + r) / np.where(np.abs(st) > 1e-14, st, 1.0) - 1.0, -1.0)
+    b = np.where(np.abs(1.0 - t) > 1e-14, 2.0 * (1.0 + s) / np.where(np.abs(1.0 - t) > 1e-14, 1.0 - t, 1.0) - 1.0,
+                 -1.0)
+    c = t
+    cols = []
+    for i in range(P + 1):
+        for j in range(P + 1 - i):
+            for k in range(P + 1 - i - j):
+                cols.append(2.0 * math.sqrt(2.0) * jn(a, 0, 0, i) * jn(b, 2 * i + 1, 0, j) * (1.0 - b) ** i
+                            * jn(c, 2 * i + 2 * j + 2, 0, k) * (1.0 - c) ** (i + j))
+    return np.stack(cols, 1)
+
+
 @functools.lru_cache(maxsize=None)
 def ref(P):
     return RefTet(P)
@@ -102,39 +133,33 @@ class RefTet:
         Vi = np.linalg.inv(V)
         self.V = V
         self.Dr, self.Ds, self.Dt = Vr @ Vi, Vs @ Vi, Vt @ Vi
-        # exact integrals over the reference tetrahedron (dV = 8 dx dy dz on
-        # the unit simplex): int x^a y^b z^c = 8 a! b! c! / (a + b + c + 3)!
-        n = len(mons)
-        Mm = np.zeros((n, n))
-        for p, (a1, b1, c1) in enumerate(mons):
-            for q, (a2, b2, c2) in enumerate(mons):
-                a, b, c = a1 + a2, b1 + b2, c1 + c2
-                Mm[p, q] = 8.0 * math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 3)
-        self.M = Vi.T @ Mm @ Vi
+        # mass matrices through an orthonormal basis: with V_o the
+        # Vandermonde matrix of a basis orthonormal on the element,
+        # M = (V_o V_o^T)^-1 exactly (the nodal basis is V_o^-T times the
+        # modal one).  Better conditioned than exact monomial moments, whose
+        # Hilbert-like matrix loses about 1e-11 at P = 4.
+        Vo = orthonormal_vandermonde3(P, self.r, self.s, self.t)
+        self.Vo = Vo
+        self.M = np.linalg.inv(Vo @ Vo.T)
         # faces: nodes by lattice condition, in increasing node order
         i, j, k = L[:, 0], L[:, 1], L[:, 2]
         conds = (k == 0, j == 0, i + j + k == P, i == 0)
         self.Fmask = np.array([np.nonzero(cnd)[0] for cnd in conds])
-        # face coordinates (u, v) on the unit triangle for each face's nodes
+        # face coordinates (u, v) on the unit triangle for each face's nodes;
+        # the face mass matrix of the face's Lagrange basis with respect to
+        # the reference triangle of area 2 (coordinates 2u - 1, 2v - 1)
         fuv = (np.stack([x, y], 1), np.stack([x, z], 1), np.stack([y, z], 1), np.stack([y, z], 1))
-        fm = [(a, b) for a in range(P + 1) for b in range(P + 1 - a)]
-        Mf_m = np.zeros((len(fm), len(fm)))
-        for p, (a1, b1) in enumerate(fm):
-            for q, (a2, b2) in enumerate(fm):
-                a, b = a1 + a2, b1 + b2
-                # unit right triangle (area 1/2) scaled to area 2: factor 4
-                Mf_m[p, q] = 4.0 * math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
         E = np.zeros((self.Np, 4 * self.Nfp))
         self.Mface = []
         for f in range(4):
             uv = fuv[f][self.Fmask[f]]
-            Vf = np.stack([uv[:, 0] ** a * uv[:, 1] ** b for a, b in fm], 1)
-            Vfi = np.linalg.inv(Vf)
-            Mf = Vfi.T @ Mf_m @ Vfi
+            Vf = orthonormal_vandermonde2(P, 2.0 * uv[:, 0] - 1.0, 2.0 * uv[:, 1] - 1.0)
+            Mf = np.linalg.inv(Vf @ Vf.T)
             self.Mface.append(Mf)
             E[np.ix_(self.Fmask[f], np.arange(f * self.Nfp, (f + 1) * self.Nfp))] = Mf
         self.E = E
-        self.LIFT = np.linalg.solve(self.M, E)
+        # LIFT = M^-1 E = V_o V_o^T E
+        self.LIFT = Vo @ (Vo.T @ E)
 
 
 # ---------------------------------------------------------------------------
@@ -341,59 +366,12 @@ RK_B = (1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
 # meshes and flows
 # ---------------------------------------------------------------------------
 
-# The 6 tetrahedra of a cube that share its main diagonal (0,0,0)-(1,1,1):
-# one per ordering of the axes along which the path from corner 0 climbs.
-_KUHN = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
-
-
 def cube_mesh(N, L=1.0, jitter=0.0, seed=0, periodic=True):
-    """N^3 cubes of side L/N, each split into 6 tetrahedra along its main
-    diagonal; vertices jittered by up to jitter * h per axis (a periodic
-    mesh jitters each shared vertex once, its images by the same amount).
-    Positively oriented elements."""
-    h = L / N
-    rng = np.random.default_rng(seed)
-    nv = N if periodic else N + 1
-    base = np.stack(np.meshgrid(np.arange(nv), np.arange(nv), np.arange(nv), indexing="ij"), -1).reshape(-1, 3)
-    VXYZ = base * h
-    if jitter > 0:
-        J = rng.uniform(-jitter * h, jitter * h, VXYZ.shape)
-        if not periodic:
-            onb = (base == 0) | (base == N)
-            J[onb] = 0.0
-        VXYZ = VXYZ + J
-
-    def vid(i, j, k):
-        if periodic:
-            return ((i % N) * N + (j % N)) * N + (k % N)
-        return (i * nv + j) * nv + k
-
-    EToV, X = [], []
-    for i in range(N):
-        for j in range(N):
-            for k in range(N):
-                for perm in _KUHN:
-                    corner = [i, j, k]
-                    path = [tuple(corner)]
-                    for ax in perm:
-                        corner[ax] += 1
-                        path.append(tuple(corner))
-                    ids = [vid(*c) for c in path]
-                    pts = []
-                    for c, v in zip(path, ids):
-                        p = VXYZ[v].copy()
-                        if periodic:
-                            p = p + (np.array(c) - np.array(c) % N) * h
-                        pts.append(p)
-                    pts = np.array(pts)
-                    vol = np.linalg.det(np.stack([pts[1] - pts[0], pts[2] - pts[0], pts[3] - pts[0]], 1))
-                    if vol < 0:
-                        ids[1], ids[2] = ids[2], ids[1]
-                        pts[[1, 2]] = pts[[2, 1]]
-                    EToV.append(ids)
-                    X.append(pts)
-    period = np.array([L, L, L]) if periodic else None
-    return TetMesh(np.array(EToV), np.array(X), period)
+    """The seeded cube mesh of the shared input generator (Kuhn split of N^3
+    cubes, jittered vertices) with this module's own connectivity."""
+    from meshgen.tets import cube_tets
+    g = cube_tets(N, L, jitter, seed, periodic)
+    return TetMesh(g.EToV, g.X, g.period)
 
 
 def primitive_to_conserved(rho, u, v, w, p, g=GAMMA):

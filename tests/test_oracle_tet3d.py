@@ -209,3 +209,65 @@ def test_entropy_wave_converges(P):
         w = o.geo.J[:, None] * o.R.M.sum(0)[None, :]
         errs.append(math.sqrt((w * (U[:, 0] - wave(o.xyz, t)[:, 0]) ** 2).sum()))
     assert math.log2(errs[0] / errs[1]) >= P + 0.2, errs
+
+
+def _exact_lift(P):
+    """LIFT of the equispaced tetrahedron in exact rational arithmetic, from
+    the definitions with the monomial basis: M from the exact simplex
+    moments 8 a! b! c! / (a+b+c+3)!, face mass matrices from the exact
+    triangle moments 4 a! b! / (a+b+2)! (area 2), LIFT = M^-1 E."""
+    from fractions import Fraction as Fr
+    f = math.factorial
+
+    def inv(A):
+        n = len(A)
+        A = [row[:] + [Fr(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+        for c in range(n):
+            p = next(r for r in range(c, n) if A[r][c] != 0)
+            A[c], A[p] = A[p], A[c]
+            d = A[c][c]
+            A[c] = [x / d for x in A[c]]
+            for r in range(n):
+                if r != c and A[r][c] != 0:
+                    m = A[r][c]
+                    A[r] = [x - m * y for x, y in zip(A[r], A[c])]
+        return [row[n:] for row in A]
+
+    def mm(A, B):
+        return [[sum(a * b for a, b in zip(row, col)) for col in zip(*B)] for row in A]
+
+    def tr(A):
+        return [list(r) for r in zip(*A)]
+
+    lat = T.lattice(P)
+    x = [Fr(int(i), P) for i in lat[:, 0]]
+    y = [Fr(int(j), P) for j in lat[:, 1]]
+    z = [Fr(int(k), P) for k in lat[:, 2]]
+    mons = [(a, b, c) for a in range(P + 1) for b in range(P + 1 - a) for c in range(P + 1 - a - b)]
+    V = [[x[n] ** a * y[n] ** b * z[n] ** c for a, b, c in mons] for n in range(len(lat))]
+    Vi = inv(V)
+    Mm = [[Fr(8 * f(a1 + a2) * f(b1 + b2) * f(c1 + c2), f(a1 + a2 + b1 + b2 + c1 + c2 + 3))
+           for a2, b2, c2 in mons] for a1, b1, c1 in mons]
+    M = mm(mm(tr(Vi), Mm), Vi)
+    fm = [(a, b) for a in range(P + 1) for b in range(P + 1 - a)]
+    Mfm = [[Fr(4 * f(a1 + a2) * f(b1 + b2), f(a1 + a2 + b1 + b2 + 2)) for a2, b2 in fm] for a1, b1 in fm]
+    Np, Nfp = len(lat), len(fm)
+    E = [[Fr(0)] * (4 * Nfp) for _ in range(Np)]
+    i, j, k = lat[:, 0], lat[:, 1], lat[:, 2]
+    for fc, cond in enumerate((k == 0, j == 0, i + j + k == P, i == 0)):
+        ids = [int(n) for n in np.nonzero(cond)[0]]
+        uv = [(x[n], y[n]) if fc == 0 else (x[n], z[n]) if fc == 1 else (y[n], z[n]) for n in ids]
+        Vf = [[u ** a * v ** b for a, b in fm] for u, v in uv]
+        Vfi = inv(Vf)
+        Mf = mm(mm(tr(Vfi), Mfm), Vfi)
+        for a in range(Nfp):
+            for b in range(Nfp):
+                E[ids[a]][fc * Nfp + b] = Mf[a][b]
+    return np.array([[float(v) for v in row] for row in mm(inv(M), E)])
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_lift_matches_exact_rational_arithmetic(P):
+    """LIFT against its definition evaluated in exact rational arithmetic
+    (a different basis and no rounding): agreement to FP64 rounding."""
+    np.testing.assert_allclose(T.ref(P).LIFT, _exact_lift(P), rtol=0, atol=5e-14 * (P + 1) ** 2)
