@@ -46,7 +46,17 @@ WORKLOADS = {
     "airfoil": "Transonic flow, Mach 0.8, AoA 1.25 deg, 4-digit 12% airfoil, far field R=30, "
                "120,000 triangles, cubic curved wall, P=3 (Np=10), Persson-Peraire sensor + "
                "LDG artificial viscosity, CFL 0.5, start from the freestream damped to rest at the wall",
+    "tet3d": "3D Euler entropy wave (rho = 1 + 0.2 sin 2 pi x, velocity (1, 0.5, 0.25), p = 1) on a "
+             "seeded, jittered periodic box of 16x16x17 cubes split into 26,112 straight tetrahedra "
+             "(the paper's timing mesh has 25,956 cells), P=4 (Np=35, 5 fields), LF flux, CFL 0.5, "
+             "200 steps; the time table at P=2,3,4 in FP64 and FP32",
 }
+
+# The paper's run times for 200 steps on 25,956 tetrahedra (Table time_table;
+# one Tesla M2050 and a 4-core Xeon E5620): context, not the target.
+PAPER_TIME_TABLE_S = {"P4": {"cpu_4core": 278.92, "gpu_fp64": 54.16, "gpu_fp32": 15.27},
+                      "P3": {"cpu_4core": 92.88, "gpu_fp64": 21.34, "gpu_fp32": 7.96},
+                      "P2": {"cpu_4core": 34.01, "gpu_fp64": 8.40, "gpu_fp32": 3.52}}
 
 
 def log(*a):
@@ -191,6 +201,125 @@ def cpu_baseline(case, budget_s=12.0):
                 cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
+def tet3d_stage_bytes(grid, P, s):
+    """HBM bytes one 3D stage launch must move (averaged over the 5 stages):
+    state in and out and the Runge-Kutta register (read in 4 of 5 stages,
+    written in all), the neighbours' face traces once per interior face
+    side, 25 geometric factors per element, and 16 bytes of connectivity
+    (four neighbour ids with their face and orientation codes) per element.
+    The kernel reads a face node map instead (4 Nfp ints per element); that
+    excess is the kernel's, so it is not counted here."""
+    K, Np, Nfp = grid.K, (P + 1) * (P + 2) * (P + 3) // 6, (P + 1) * (P + 2) // 2
+    interior_sides = int((grid.bc == 0).sum())
+    state = K * 5 * Np * s * (3 + 4 / 5)
+    traces = interior_sides * Nfp * 5 * s
+    return state + traces + K * 25 * s + 16 * K
+
+
+def bench_tet3d(args, dev):
+    """The 3D workload: 200 LSERK steps on the 26,112-tetrahedron box at
+    P = 4 (the timed line) and the time table at P = 2, 3, 4 in FP64 and
+    FP32, beside the paper's run times (context) and the oracle on this
+    host's cores."""
+    import numpy as np
+    import torch
+
+    from meshgen.tets import affine_node_coordinates, cube_tets, entropy_wave3
+    from paper_1208_4772_amd import dg3
+    steps = 200 if args.steps is None else args.steps
+    grid = cube_tets((16, 16, 17), 1.0, 0.1, 3, periodic=True)
+    log(f"workload tet3d: K={grid.K} steps={steps} warmup={args.warmup}")
+
+    def timed(P, precision, nsteps, warmup):
+        sol = dg3.Solver3D.from_mesh(grid, P, precision=precision, cfl=0.5)
+        r, s_, t = dg3.reference_nodes3(P)
+        U0 = sol.state(entropy_wave3(affine_node_coordinates(grid, r, s_, t), along=(1, 0, 0)))
+        U = U0.clone()
+        if warmup:
+            sol.run(U, warmup)
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sol.run(U, nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ok = bool(torch.isfinite(U).all().item())
+        out = (wall, st, ok, sol.dofs(), U.double().cpu().numpy())
+        sol.close()
+        return out
+
+    table = {}
+    final = {}
+    main_line = None
+    for P in (4, 3, 2):
+        row = {}
+        for precision in ("fp32", "fp64"):
+            wall, st, ok, dofs, Uf = timed(P, precision, steps, args.warmup)
+            if not ok or st.status != 0:
+                raise SystemExit(f"tet3d P={P} {precision}: state became non-finite")
+            row[precision] = dict(seconds=round(wall, 5), dof_updates_per_s=dofs * 5 * steps / wall,
+                                  device_s=round(st.wall_s, 5), t=st.t)
+            final[(P, precision)] = Uf
+            log(f"tet3d P={P} {precision}: {wall * 1e3:.2f} ms for {steps} steps -> "
+                f"{dofs * 5 * steps / wall:.4e} DOF-updates/s")
+            if P == 4 and precision == "fp32":
+                main_line = (wall, st, dofs)
+        d = final[(P, "fp32")] - final[(P, "fp64")]
+        row["fp32_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(final[(P, "fp64")]))
+        row["fp32_vs_fp64_max_abs"] = float(np.abs(d).max())
+        row["fp64_over_fp32_time"] = round(row["fp64"]["seconds"] / row["fp32"]["seconds"], 3)
+        table[f"P{P}"] = row
+    wall, st, dofs = main_line
+    value = dofs * 5 * steps / wall
+    # device events bracket the steps: 5 stage launches and the step's bound
+    # and dt kernels per step, so this average slightly overstates the stage
+    # kernel's own duration
+    avg_s = st.wall_s / (5 * steps)
+    launch_bytes = tet3d_stage_bytes(grid, 4, 4)
+    achieved = launch_bytes / avg_s / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["tet3d"], "K": grid.K, "P": 4, "dof": dofs, "precision": "fp32"},
+        "roofline": dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_stage3<float,4>",
+                         avg_launch_us=round(avg_s * 1e6, 3), launches=5 * steps,
+                         algorithmic_bytes_per_launch=int(launch_bytes),
+                         note="average over the stage launches of the timed region, the per-step "
+                              "bound kernels included"),
+        "time_table_200_steps": table,
+        "paper_time_table_s": PAPER_TIME_TABLE_S,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_tet3d(grid, min(args.cpu_budget, 20.0))
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_tet3d(grid, budget_s):
+    """The FP64 3D oracle at P = 4 on the same mesh: rhs evaluations (one RK
+    stage each) for about budget_s seconds.  Its contractions are NumPy
+    einsums, which run on one thread."""
+    from meshgen.tets import entropy_wave3
+    from oracle import tet3d as T
+    o = T.Oracle3D(T.TetMesh(grid.EToV, grid.X, grid.period), 4)
+    U = entropy_wave3(o.xyz, along=(1, 0, 0))
+    t0 = time.perf_counter()
+    o.rhs(U)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(budget_s / t1))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        o.rhs(U)
+    el = time.perf_counter() - t0
+    dofs = grid.K * 5 * o.R.Np
+    return dict(value=dofs * n / el, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=f"{n} rhs evaluations (RK stages) of the {grid.K}-tetrahedron P=4 mesh, FP64, "
+                       f"{el:.1f} s; 200 steps at this rate: {1000 * el / n:.0f} s",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count())
+
+
 def copy_peak(dev, gib=1.0, reps=10):
     """Device-to-device copy of `gib` GiB: the practical HBM rate (read plus
     write bytes per second) and the time of one copy in ms."""
@@ -272,6 +401,9 @@ def main():
         n = int(args.copy_probe * (1 << 30)) // 4
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
                           "avg_ms": ms, "achieved_GBs": gbs}), flush=True)
+        return
+    if args.workload == "tet3d":
+        bench_tet3d(args, dev)
         return
     P = {"cylinder": 4, "roofline": 5, "vortex": 2, "airfoil": 3}[args.workload]
     r, s = dg.reference_nodes(P)

@@ -73,6 +73,8 @@ int tuned_waves(const std::string &arch, int P, int precision, int av) {
 
 }  // namespace
 
+int dg::report_error(int code, const std::string &msg) { return fail(code, msg); }
+
 struct dg_mesh {
     DevMesh dm;
     // unique per handle over the process's life (an address can be reused

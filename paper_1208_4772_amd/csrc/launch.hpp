@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
 
 namespace dg {
 
@@ -187,5 +188,32 @@ hipError_t launch_stage_weak(const DevMesh &m, const void *Uin, void *Uout, void
 constexpr int kProlongMax = 21 * 21;
 hipError_t launch_prolong(int K, int np_from, int np_to, const double *I, bool fp32, const void *Uf, void *Ut,
                           hipStream_t st);
+
+// ---- 3D tetrahedra (tet3d.hip, api3.cpp)
+struct Tet3Mesh {
+    int K = 0, P = 0, Np = 0, Nfp = 0;
+    bool fp32 = false;
+    double gamma = 1.4, cfl = 0.5;
+    const double *geo64 = nullptr;   // [K][25]
+    const float *geo32 = nullptr;
+    const double *ops64 = nullptr;   // Dr | Ds | Dt | LIFT
+    const float *ops32 = nullptr;
+    const int *fmap = nullptr;       // [K][4 Nfp]
+    const int *fmask = nullptr;      // [4 Nfp]
+    double *scal = nullptr;          // [S_NSCAL]
+    unsigned long long *vmax = nullptr;
+    int *flag = nullptr;
+};
+int tet3_blocks(int K, int P, bool fp32);
+hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hipStream_t st);
+// zeroes the scalars (dt_min = +inf), the bound and the flag
+hipError_t launch_reset3(const Tet3Mesh &m, hipStream_t st);
+hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                         hipStream_t st);
+// time-step bound (FP64, from the state) and dt = CFL / bound (dt_fixed > 0
+// overrides) into scal; raises *flag on bad states
+hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStream_t st);
+// error reporting shared with the 2D ABI (dg_last_error)
+int report_error(int code, const std::string &msg);
 
 }  // namespace dg

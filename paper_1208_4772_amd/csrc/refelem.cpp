@@ -213,6 +213,8 @@ void gauss_jacobi(int n, double a, double b, std::vector<double> &x, std::vector
 
 }  // namespace
 
+double jacobi_orthonormal(double x, double a, double b, int n) { return jacobi(x, a, b, n); }
+
 bool build_weak(int P, WeakOps &w) {
     RefOps o;
     if (!build_reference(P, o)) return false;

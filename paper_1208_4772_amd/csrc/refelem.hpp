@@ -39,4 +39,8 @@ inline int weak_points_per_direction(int P) { return (3 * P + 2) / 2; }
 
 inline int n_nodes(int P) { return (P + 1) * (P + 2) / 2; }
 
+// Jacobi polynomial p_n^(a,b)(x) of unit norm on [-1,1] under the weight
+// (1-x)^a (1+x)^b.
+double jacobi_orthonormal(double x, double a, double b, int n);
+
 }  // namespace dg

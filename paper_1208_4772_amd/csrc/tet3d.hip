@@ -1,0 +1,361 @@
+// 3D nodal DG on straight tetrahedra, five fields (rho, rho u, rho v, rho w,
+// E): the paper's own setting (Section 2; the 3D Euler system of Section 5).
+//
+//   dU/dt = -(r_x Dr + s_x Ds + t_x Dt) F - (r_y ...) G - (r_z ...) H
+//           + LIFT (Fscale (n.F(U-) - F*)),   F* local Lax-Friedrichs
+//
+// on a reference tetrahedron with vertices (-1,-1,-1), (1,-1,-1), (-1,1,-1),
+// (-1,-1,1), faces (v1 v2 v3), (v1 v2 v4), (v2 v3 v4), (v1 v3 v4), and
+// equispaced nodes (the lattice (i, j, k)/P, r fastest).  A straight element
+// has constant metric terms, normals and Fscale per face: 25 numbers.
+//
+// One block holds up to floor(256 / Np) elements (fewer where their LDS
+// would pass 48 KB), one thread per node:
+// pointwise contravariant fluxes into LDS, the volume term from the
+// reference derivative matrices (global memory, cached), one thread per
+// face node for the flux jumps (neighbour traces gathered through a
+// precomputed node map), LIFT, and the low-storage Runge-Kutta update.
+// The time step is reduced in FP64 from the state (k_cfl3, k_dt3).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace dg {
+namespace {
+
+constexpr int kF3 = 5;          // fields
+constexpr int kB3 = 256;        // threads per block
+constexpr int kGeo3 = 25;       // r_x r_y r_z s_x s_y s_z t_x t_y t_z | (n_x n_y n_z) x 4 | Fscale x 4
+
+// Elements per block: one thread per node, and at most 48 KB of LDS (the
+// tile, its contravariant fluxes, its face jumps and its geometry).
+template <typename T, int P>
+struct Tet {
+    static constexpr int Np = (P + 1) * (P + 2) * (P + 3) / 6;
+    static constexpr int Nfp = (P + 1) * (P + 2) / 2;
+    static constexpr int NF4 = 4 * Nfp;
+    static constexpr int per = (kF3 * Np + 3 * kF3 * Np + kF3 * NF4 + kGeo3) * int(sizeof(T));
+    static constexpr int by_lds = (48 * 1024) / per;
+    static constexpr int EB = (kB3 / Np) < by_lds ? (kB3 / Np) : by_lds;
+};
+
+template <typename T>
+struct Stage3Args {
+    int K, stage, mode;
+    T g, ra, rb;
+    const T *__restrict__ Uin;
+    T *__restrict__ Uout;
+    T *__restrict__ R;
+    T *__restrict__ rhs;
+    const T *__restrict__ geo;     // [K][25]
+    const int *__restrict__ fmap;  // [K][4 Nfp]: neighbour node base (kn*5*Np + node), -1 at a wall
+    const int *__restrict__ fmask; // [4 Nfp] face node -> volume node
+    const T *__restrict__ ops;     // Dr | Ds | Dt (Np x Np, row-major) | LIFT (Np x 4 Nfp)
+    const double *__restrict__ dt;
+};
+
+template <typename T>
+__device__ inline void euler3_flux(T g, const T u[kF3], T F[kF3], T G[kF3], T H[kF3]) {
+    const T ir = rcp(u[0]);
+    const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const T p = (g - T(1)) * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+    F[0] = u[1]; F[1] = u[1] * vx + p; F[2] = u[2] * vx; F[3] = u[3] * vx; F[4] = (u[4] + p) * vx;
+    G[0] = u[2]; G[1] = u[1] * vy; G[2] = u[2] * vy + p; G[3] = u[3] * vy; G[4] = (u[4] + p) * vy;
+    H[0] = u[3]; H[1] = u[1] * vz; H[2] = u[2] * vz; H[3] = u[3] * vz + p; H[4] = (u[4] + p) * vz;
+}
+
+// n.F(u) and |v.n| + c
+template <typename T>
+__device__ inline void normal_flux3(T g, const T u[kF3], T nx, T ny, T nz, T fn[kF3], T &lam) {
+    const T ir = rcp(u[0]);
+    const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const T p = (g - T(1)) * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+    const T vn = vx * nx + vy * ny + vz * nz;
+    fn[0] = u[0] * vn;
+    fn[1] = u[1] * vn + p * nx;
+    fn[2] = u[2] * vn + p * ny;
+    fn[3] = u[3] * vn + p * nz;
+    fn[4] = (u[4] + p) * vn;
+    lam = fabs(vn) + fsqrt(g * p * ir);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kB3) void k_stage3(Stage3Args<T> a) {
+    using S = Tet<T, P>;
+    constexpr int Np = S::Np, NF4 = S::NF4, EB = S::EB;
+    __shared__ T sU[EB][kF3][Np];
+    __shared__ T sC[EB][3][kF3][Np];     // contravariant fluxes along r, s, t
+    __shared__ T sJ[EB][kF3][NF4];       // Fscale (n.F(U-) - F*) at the face nodes
+    __shared__ T sG[EB][kGeo3];
+    const long k0 = (long)blockIdx.x * EB;
+    const int nel = (int)min((long)EB, (long)a.K - k0);
+    const int tid = threadIdx.x;
+    for (int z = tid; z < nel * kF3 * Np; z += kB3) (&sU[0][0][0])[z] = a.Uin[k0 * kF3 * Np + z];
+    for (int z = tid; z < nel * kGeo3; z += kB3) (&sG[0][0])[z] = a.geo[k0 * kGeo3 + z];
+    __syncthreads();
+
+    const int el = tid / Np, i = tid - el * Np;
+    const bool act = el < nel;
+    if (act) {
+        T u[kF3], F[kF3], G[kF3], H[kF3];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) u[c] = sU[el][c][i];
+        euler3_flux(a.g, u, F, G, H);
+        const T *m = sG[el];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < kF3; ++c) sC[el][d][c][i] = m[3 * d] * F[c] + m[3 * d + 1] * G[c] + m[3 * d + 2] * H[c];
+    }
+    // face-node tasks: (element, face node)
+    for (int z = tid; z < nel * NF4; z += kB3) {
+        const int e = z / NF4, q = z - e * NF4, f = q / (NF4 / 4);
+        const long k = k0 + e;
+        const int vm = a.fmask[q];
+        T um[kF3], up[kF3];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) um[c] = sU[e][c][vm];
+        const T nx = sG[e][9 + 3 * f], ny = sG[e][10 + 3 * f], nz = sG[e][11 + 3 * f], fs = sG[e][21 + f];
+        const int base = a.fmap[k * NF4 + q];
+        if (base >= 0) {
+#pragma unroll
+            for (int c = 0; c < kF3; ++c) up[c] = a.Uin[(long)base + c * Np];
+        } else {
+            // slip wall: the mirror state
+            const T mn = um[1] * nx + um[2] * ny + um[3] * nz;
+            up[0] = um[0];
+            up[1] = um[1] - T(2) * mn * nx;
+            up[2] = um[2] - T(2) * mn * ny;
+            up[3] = um[3] - T(2) * mn * nz;
+            up[4] = um[4];
+        }
+        T fm[kF3], fp[kF3], lm, lp;
+        normal_flux3(a.g, um, nx, ny, nz, fm, lm);
+        normal_flux3(a.g, up, nx, ny, nz, fp, lp);
+        const T lam = lm > lp ? lm : lp;
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) sJ[e][c][q] = fs * (T(0.5) * (fm[c] - fp[c]) + T(0.5) * lam * (up[c] - um[c]));
+    }
+    __syncthreads();
+    if (!act) return;
+    const T *Dr = a.ops, *Ds = Dr + Np * Np, *Dt = Ds + Np * Np, *LIFT = Dt + Np * Np;
+    T r[kF3] = {};
+#pragma unroll 2
+    for (int j = 0; j < Np; ++j) {
+        const T dr = Dr[i * Np + j], ds = Ds[i * Np + j], dt = Dt[i * Np + j];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) r[c] -= dr * sC[el][0][c][j] + ds * sC[el][1][c][j] + dt * sC[el][2][c][j];
+    }
+#pragma unroll 2
+    for (int m = 0; m < NF4; ++m) {
+        const T l = LIFT[i * NF4 + m];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) r[c] += l * sJ[el][c][m];
+    }
+    const long k = k0 + el;
+    const T dt = a.mode ? T(*a.dt) : T(0);
+#pragma unroll
+    for (int c = 0; c < kF3; ++c) {
+        const long idx = (k * kF3 + c) * Np + i;
+        if (a.mode == 0) {
+            a.rhs[idx] = r[c];
+        } else {
+            const T rr = a.stage == 0 ? dt * r[c] : a.ra * a.R[idx] + dt * r[c];
+            a.R[idx] = rr;
+            a.Uout[idx] = sU[el][c][i] + a.rb * rr;
+        }
+    }
+}
+
+// Time-step bound in FP64 at every face node: (P+1)^2 Fscale (|v| + c) / 2,
+// maximum per block into *vmax (non-negative doubles order like their bit
+// patterns); the state check (non-finite, rho <= 0, p <= 0) at every face
+// node.
+template <typename T, int P>
+__global__ __launch_bounds__(kB3) void k_cfl3(int K, double g, const T *__restrict__ U, const T *__restrict__ geo,
+                                             const int *__restrict__ fmask, unsigned long long *vmax,
+                                             int *flag) {
+    using S = Tet<T, P>;
+    constexpr int Np = S::Np, NF4 = S::NF4, EB = S::EB;
+    __shared__ double sRed[kB3 / 64];
+    const long k0 = (long)blockIdx.x * EB;
+    const int nel = (int)min((long)EB, (long)K - k0);
+    double best = 0.0;
+    int bad = 0;
+    for (int z = threadIdx.x; z < nel * NF4; z += kB3) {
+        const int e = z / NF4, q = z - e * NF4, f = q / (NF4 / 4);
+        const long k = k0 + e;
+        const int v = fmask[q];
+        double u[kF3];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) u[c] = double(U[(k * kF3 + c) * Np + v]);
+        const double ir = 1.0 / u[0];
+        const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+        const double p = (g - 1.0) * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
+        if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+            !isfinite(u[4]) || !isfinite(p))
+            bad = 1;
+        const double lam = sqrt(vx * vx + vy * vy + vz * vz) + sqrt(g * p * ir);
+        const double fs = double(geo[k * kGeo3 + 21 + f]);
+        const double b = 0.5 * (P + 1.0) * (P + 1.0) * fs * lam;
+        best = b > best ? b : best;
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(best, off);
+        best = o > best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sRed[0];
+        for (int w = 1; w < kB3 / 64; ++w) m = sRed[w] > m ? sRed[w] : m;
+        atomicMax(vmax, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// dt = CFL / bound (or the fixed step), booked into the scalars; clears the
+// bound for the next step.
+__global__ void k_dt3(double cfl, double dt_fixed, unsigned long long *vmax, double *scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double b = __longlong_as_double((long long)*vmax);
+    const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / b;
+    scal[S_DT] = dt;
+    scal[S_T] += dt;
+    scal[S_DTMIN] = dt < scal[S_DTMIN] ? dt : scal[S_DTMIN];
+    scal[S_DTMAX] = dt > scal[S_DTMAX] ? dt : scal[S_DTMAX];
+    scal[S_STEPS] += 1.0;
+    *vmax = 0ull;
+}
+
+// Straight-element geometry in FP64: metric terms from the vertex
+// coordinates (the affine map's columns x_r = (v2 - v1)/2, ...), outward unit
+// normals and Fscale = (face area / 2) / (volume / (4/3)) per face.
+__global__ void k_geometry3(int K, const double *__restrict__ X, double *__restrict__ geo,
+                            int *__restrict__ count) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const double *v = X + k * 12;
+    double A[3][3];   // A[d][a] = d x_d / d r_a
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) A[d][c] = 0.5 * (v[3 * (c + 1) + d] - v[d]);
+    const double J = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(J > 0.0)) atomicAdd(count, 1);
+    double *g = geo + k * kGeo3;
+    // inverse: row a of A^-1 is grad r_a
+    const double iJ = 1.0 / J;
+    g[0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) * iJ;
+    g[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * iJ;
+    g[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * iJ;
+    g[3] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) * iJ;
+    g[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * iJ;
+    g[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * iJ;
+    g[6] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) * iJ;
+    g[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * iJ;
+    g[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * iJ;
+    const int fv[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {0, 2, 3}};
+    const int opp[4] = {3, 2, 0, 1};
+    for (int f = 0; f < 4; ++f) {
+        const double *pa = v + 3 * fv[f][0], *pb = v + 3 * fv[f][1], *pc = v + 3 * fv[f][2], *po = v + 3 * opp[f];
+        const double e1[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+        const double e2[3] = {pc[0] - pa[0], pc[1] - pa[1], pc[2] - pa[2]};
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double twice_area = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const double toward = n[0] * (po[0] - pa[0]) + n[1] * (po[1] - pa[1]) + n[2] * (po[2] - pa[2]);
+        const double sgn = toward > 0.0 ? -1.0 : 1.0;
+        for (int d = 0; d < 3; ++d) g[9 + 3 * f + d] = sgn * n[d] / twice_area;
+        g[21 + f] = (0.25 * twice_area) / J;
+    }
+}
+
+__global__ void k_reset3(double *scal, unsigned long long *vmax, int *flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < S_NSCAL; ++i) scal[i] = 0.0;
+    scal[S_DTMIN] = __longlong_as_double(0x7ff0000000000000ll);   // +inf
+    *vmax = 0ull;
+    *flag = 0;
+}
+
+template <typename F>
+auto with_order3(int P, F &&f) {
+    switch (P) {
+        case 1: return f(std::integral_constant<int, 1>());
+        case 2: return f(std::integral_constant<int, 2>());
+        case 3: return f(std::integral_constant<int, 3>());
+        default: return f(std::integral_constant<int, 4>());
+    }
+}
+
+}  // namespace
+
+int tet3_blocks(int K, int P, bool fp32) {
+    return with_order3(P, [&](auto PC) {
+        constexpr int P_ = decltype(PC)::value;
+        const int EB = fp32 ? Tet<float, P_>::EB : Tet<double, P_>::EB;
+        return (K + EB - 1) / EB;
+    });
+}
+
+hipError_t launch_reset3(const Tet3Mesh &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset3, dim3(1), dim3(64), 0, st, m.scal, m.vmax, m.flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_geometry3, dim3((K + 127) / 128), dim3(128), 0, st, K, X, geo, count);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t stage3_t(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                           hipStream_t st) {
+    Stage3Args<T> a;
+    a.K = m.K;
+    a.stage = stage;
+    a.mode = rhs ? 0 : 1;
+    a.g = T(m.gamma);
+    a.ra = T(rk_a(stage));
+    a.rb = T(rk_b(stage));
+    a.Uin = static_cast<const T *>(Uin);
+    a.Uout = static_cast<T *>(Uout);
+    a.R = static_cast<T *>(R);
+    a.rhs = static_cast<T *>(rhs);
+    a.geo = static_cast<const T *>(m.fp32 ? static_cast<const void *>(m.geo32) : m.geo64);
+    a.fmap = m.fmap;
+    a.fmask = m.fmask;
+    a.ops = static_cast<const T *>(m.fp32 ? static_cast<const void *>(m.ops32) : m.ops64);
+    a.dt = m.scal + S_DT;
+    return with_order3(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL((k_stage3<T, P>), dim3(tet3_blocks(m.K, P, m.fp32)), dim3(kB3), 0, st, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                         hipStream_t st) {
+    return m.fp32 ? stage3_t<float>(m, Uin, Uout, R, rhs, stage, st)
+                  : stage3_t<double>(m, Uin, Uout, R, rhs, stage, st);
+}
+
+hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStream_t st) {
+    hipError_t e = with_order3(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        const dim3 grid(tet3_blocks(m.K, P, m.fp32)), block(kB3);
+        if (m.fp32)
+            hipLaunchKernelGGL((k_cfl3<float, P>), grid, block, 0, st, m.K, m.gamma, static_cast<const float *>(U),
+                               m.geo32, m.fmask, m.vmax, m.flag);
+        else
+            hipLaunchKernelGGL((k_cfl3<double, P>), grid, block, 0, st, m.K, m.gamma, static_cast<const double *>(U),
+                               m.geo64, m.fmask, m.vmax, m.flag);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dt3, dim3(1), dim3(64), 0, st, m.cfl, dt_fixed, m.vmax, m.scal);
+    return hipGetLastError();
+}
+
+}  // namespace dg

@@ -37,6 +37,9 @@ EXPORTS = ("dg_last_error", "dg_version", "dg_reference_nodes", "dg_face_nodes",
            "dg_status", "dg_step_static", "dg_prolong_operator", "dg_prolong", "dg_weak_operators",
            "dg_batch_info", "dg_tuning_set", "dg_tuning_lookup", "dg_tuning_clear", "dg_tuning_save",
            "dg_tuning_load", "dg_device_arch", "dg_mesh_curved")
+# Every symbol include/dg3.h declares.
+EXPORTS3 = ("dg3_reference_nodes", "dg3_reference_operators", "dg3_face_map", "dg3_mesh_setup",
+            "dg3_mesh_destroy", "dg3_buffer_bytes", "dg3_rhs", "dg3_run")
 
 
 class DGError(RuntimeError):
@@ -119,7 +122,16 @@ def lib():
         L.dg_tuning_load.argtypes = [cp, C.POINTER(i)]
         L.dg_device_arch.argtypes = [C.c_char_p, sz]
         L.dg_mesh_curved.argtypes = [vp, C.POINTER(i)]
-        for name in EXPORTS:
+        # the 3D ABI (include/dg3.h)
+        L.dg3_reference_nodes.argtypes = [i, vp, vp, vp]
+        L.dg3_reference_operators.argtypes = [i, vp, vp, vp, vp, vp]
+        L.dg3_face_map.argtypes = [vp, vp]
+        L.dg3_mesh_setup.argtypes = [vp, vp, C.POINTER(vp)]
+        L.dg3_mesh_destroy.argtypes = [vp]
+        L.dg3_buffer_bytes.argtypes = [vp, C.POINTER(sz), C.POINTER(sz)]
+        L.dg3_rhs.argtypes = [vp, vp, vp, vp]
+        L.dg3_run.argtypes = [vp, vp, vp, i, d, C.POINTER(RunStats), vp]
+        for name in EXPORTS + EXPORTS3:
             getattr(L, name).restype = getattr(L, name).restype or i
         _lib = L
     return _lib
