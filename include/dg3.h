@@ -16,8 +16,9 @@
  * then s, then t (Np = (P+1)(P+2)(P+3)/6, P = 1..4).
  *
  * Layouts: states are [K][5][Np] in the handle's precision (double for
- * DG_FP64_PLAIN, float for DG_FP32), on the device; every array in
- * dg3_mesh_desc is host memory, read during dg3_mesh_setup only. */
+ * DG_FP64_PLAIN, float for DG_FP32), on the device, 16-byte aligned (the
+ * work buffer too); every array in dg3_mesh_desc is host memory, read
+ * during dg3_mesh_setup only. */
 #ifndef DG3_H
 #define DG3_H
 
@@ -86,7 +87,8 @@ int dg3_mesh_destroy(dg3_mesh *mesh);
 int dg3_buffer_bytes(const dg3_mesh *mesh, size_t *state_bytes, size_t *work_bytes);
 
 /* rhs = dU/dt of the device state U (no time stepping).  Enqueues only.
- * Errors: DG_EINVAL (NULL pointers, U == rhs), DG_EDEVICE. */
+ * Errors: DG_EINVAL (NULL pointers, U == rhs, a pointer not 16-byte
+ * aligned), DG_EDEVICE. */
 int dg3_rhs(dg3_mesh *mesh, const void *U, void *rhs, void *stream);
 
 /* nsteps LSERK steps of U in place.  dt_fixed > 0: that step; otherwise

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
@@ -329,6 +330,9 @@ int connect_faces(const dg3_mesh_desc *d, const RefOps3 &o, std::vector<int> &fm
     return DG_OK;
 }
 
+// The FP32 stage moves whole tiles as 16-byte vectors.
+bool misaligned(const void *p) { return reinterpret_cast<uintptr_t>(p) % 16 != 0; }
+
 }  // namespace
 
 struct dg3_mesh {
@@ -426,13 +430,20 @@ int dg3_mesh_setup(const dg3_mesh_desc *d, void *stream, dg3_mesh **out) {
     if ((rc = h->alloc(&X_d, size_t(K) * 12)) || (rc = h->alloc(&geo64, size_t(K) * 25)) ||
         (rc = h->alloc(&ops64, nops)) || (rc = h->alloc(&fmap_d, fmap.size())) ||
         (rc = h->alloc(&fmask_d, size_t(NF4))) || (rc = h->alloc(&count_d, 1)) || (rc = h->alloc(&flag_d, 1)) ||
-        (rc = h->alloc(&scal, S_NSCAL)) || (rc = h->alloc(&vmax_d, 1)))
+        (rc = h->alloc(&scal, S_NSCAL)) || (rc = h->alloc(&vmax_d, kSlots3)))
         return cleanup(rc);
-    std::vector<double> ops;
-    ops.insert(ops.end(), o.Dr.begin(), o.Dr.end());
-    ops.insert(ops.end(), o.Ds.begin(), o.Ds.end());
-    ops.insert(ops.end(), o.Dt.begin(), o.Dt.end());
-    ops.insert(ops.end(), o.LIFT.begin(), o.LIFT.end());
+    // device operators column-major (Dr^T | Ds^T | Dt^T | LIFT^T): for a
+    // fixed column the threads of an element (one per row) read consecutive
+    // words
+    std::vector<double> ops(nops);
+    for (int j = 0; j < Np; ++j)
+        for (int i = 0; i < Np; ++i) {
+            ops[size_t(j) * Np + i] = o.Dr[size_t(i) * Np + j];
+            ops[size_t(Np) * Np + size_t(j) * Np + i] = o.Ds[size_t(i) * Np + j];
+            ops[size_t(2) * Np * Np + size_t(j) * Np + i] = o.Dt[size_t(i) * Np + j];
+        }
+    for (int m = 0; m < NF4; ++m)
+        for (int i = 0; i < Np; ++i) ops[size_t(3) * Np * Np + size_t(m) * Np + i] = o.LIFT[size_t(i) * NF4 + m];
     SETUP3(hipMemcpyAsync(X_d, d->X, sizeof(double) * size_t(K) * 12, hipMemcpyHostToDevice, st));
     SETUP3(hipMemcpyAsync(ops64, ops.data(), sizeof(double) * ops.size(), hipMemcpyHostToDevice, st));
     SETUP3(hipMemcpyAsync(fmap_d, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice, st));
@@ -457,6 +468,13 @@ int dg3_mesh_setup(const dg3_mesh_desc *d, void *stream, dg3_mesh **out) {
         SETUP3(launch_cast(ops64, ops32, nops, st));
         m.geo32 = geo32;
         m.ops32 = ops32;
+        float *opsA_d;
+        const size_t nA = tet3_mfma_opsA_floats(P);
+        if ((rc = h->alloc(&opsA_d, nA))) return cleanup(rc);
+        std::vector<float> opsA(nA);
+        tet3_mfma_fill_opsA(P, o.Dr.data(), o.Ds.data(), o.Dt.data(), o.LIFT.data(), opsA.data());
+        SETUP3(hipMemcpyAsync(opsA_d, opsA.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
+        m.opsA = opsA_d;
     }
     SETUP3(launch_reset3(m, st));
     SETUP3(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
@@ -483,6 +501,7 @@ int dg3_buffer_bytes(const dg3_mesh *h, size_t *state_bytes, size_t *work_bytes)
 int dg3_rhs(dg3_mesh *h, const void *U, void *rhs, void *stream) {
     if (!h || !U || !rhs) return report_error(DG_EINVAL, "null argument");
     if (U == rhs) return report_error(DG_EINVAL, "U and rhs must not alias");
+    if (misaligned(U) || misaligned(rhs)) return report_error(DG_EINVAL, "states must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP3(launch_stage3(h->m, U, nullptr, nullptr, rhs, 0, st));
     (void)hipEventRecord(h->done, st);
@@ -492,6 +511,7 @@ int dg3_rhs(dg3_mesh *h, const void *U, void *rhs, void *stream) {
 int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_run_stats *stats, void *stream) {
     if (!h || !U || !work) return report_error(DG_EINVAL, "null argument");
     if (nsteps < 0) return report_error(DG_EINVAL, "nsteps must be >= 0");
+    if (misaligned(U) || misaligned(work)) return report_error(DG_EINVAL, "U and work must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Tet3Mesh &m = h->m;
     char *w = static_cast<char *>(work);

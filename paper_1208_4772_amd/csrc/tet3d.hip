@@ -16,7 +16,18 @@
 // face node for the flux jumps (neighbour traces gathered through a
 // precomputed node map), LIFT, and the low-storage Runge-Kutta update.
 // The time step is reduced in FP64 from the state (k_cfl3, k_dt3).
+//
+// FP32 handles run the stage on the matrix cores instead (k_stage3_mfma):
+// with constant metric terms the volume term folds into contravariant
+// fluxes, F_a = sum_d (d r_a / d x_d) F_d, and the whole right-hand side of a
+// field is one product
+//   rhs = [-Dr  -Ds  -Dt  LIFT] (Np x (3 Np + 4 Nfp)) . [F_r; F_s; F_t; Fscale (n.F - F*)],
+// formed for column groups of 3 elements x 5 fields (15 of 16 columns) with
+// v_mfma_f32_16x16x4f32; the A operand (the same few tens of KB for every
+// block) is read from the caches, the B operand is built in LDS.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -51,7 +62,7 @@ struct Stage3Args {
     const T *__restrict__ geo;     // [K][25]
     const int *__restrict__ fmap;  // [K][4 Nfp]: neighbour node base (kn*5*Np + node), -1 at a wall
     const int *__restrict__ fmask; // [4 Nfp] face node -> volume node
-    const T *__restrict__ ops;     // Dr | Ds | Dt (Np x Np, row-major) | LIFT (Np x 4 Nfp)
+    const T *__restrict__ ops;     // Dr^T | Ds^T | Dt^T (Np x Np) | LIFT^T (4 Nfp x Np): column-major operators
     const double *__restrict__ dt;
 };
 
@@ -143,13 +154,13 @@ __global__ __launch_bounds__(kB3) void k_stage3(Stage3Args<T> a) {
     T r[kF3] = {};
 #pragma unroll 2
     for (int j = 0; j < Np; ++j) {
-        const T dr = Dr[i * Np + j], ds = Ds[i * Np + j], dt = Dt[i * Np + j];
+        const T dr = Dr[j * Np + i], ds = Ds[j * Np + i], dt = Dt[j * Np + i];
 #pragma unroll
         for (int c = 0; c < kF3; ++c) r[c] -= dr * sC[el][0][c][j] + ds * sC[el][1][c][j] + dt * sC[el][2][c][j];
     }
 #pragma unroll 2
     for (int m = 0; m < NF4; ++m) {
-        const T l = LIFT[i * NF4 + m];
+        const T l = LIFT[m * Np + i];
 #pragma unroll
         for (int c = 0; c < kF3; ++c) r[c] += l * sJ[el][c][m];
     }
@@ -168,10 +179,244 @@ __global__ __launch_bounds__(kB3) void k_stage3(Stage3Args<T> a) {
     }
 }
 
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Shape of the matrix-core stage: contraction length KV = 3 Np + 4 Nfp in
+// KS k-steps of 4, MT 16-row output tiles, NT column groups (3 elements
+// each) per 4-wave block, as many as keep the block's LDS near 48 KB.  The
+// B operand is stored column-major with a column stride KPP = 4 (mod 8)
+// words: the flux writes (consecutive rows) and the fragment reads (16
+// columns x 4 rows) then spread over the LDS banks.
+template <int P>
+struct TetM {
+    static constexpr int Np = (P + 1) * (P + 2) * (P + 3) / 6;
+    static constexpr int Nfp = (P + 1) * (P + 2) / 2;
+    static constexpr int NF4 = 4 * Nfp;
+    static constexpr int KV = 3 * Np + NF4;
+    static constexpr int KS = (KV + 3) / 4;
+    static constexpr int KP = 4 * KS;
+    static constexpr int KPP = KP % 8 == 4 ? KP : KP + 4;
+    static constexpr int MT = (Np + 15) / 16;
+    static constexpr int NZ = KS * MT;            // A fragments per lane
+    static constexpr int NG4 = (NZ + 3) / 4;      // ... in 16-byte groups
+    static constexpr int W = 4;
+    static constexpr int NTH = 64 * W;
+    static constexpr int group_bytes = (16 * KPP + 3 * kF3 * Np) * 4;
+    static constexpr int nt_fit = (48 * 1024 / group_bytes) / W * W;
+    static constexpr int NT = nt_fit < W ? W : (nt_fit > 16 ? 16 : nt_fit);
+    static constexpr int EB = 3 * NT;
+    static constexpr int TPT = (EB * NF4 + NTH - 1) / NTH;   // face-node tasks per thread
+    static_assert(15 * Np <= 16 * KPP, "a group's result fits in its B block");
+};
+
+struct Stage3MArgs {
+    int K, stage, mode;
+    float g, ra, rb;
+    const float *__restrict__ Uin;
+    float *__restrict__ Uout;
+    float *__restrict__ R;
+    float *__restrict__ rhs;
+    const float *__restrict__ geo;   // [K][25]
+    const int *__restrict__ fmap;    // [K][4 Nfp]
+    const int *__restrict__ fmask;   // [4 Nfp]
+    const f32x4_t *__restrict__ opsA;  // [NG4][64]: fragment z = ks MT + mt of lane l in group z / 4, slot z % 4
+    const double *__restrict__ dt;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_stage3_mfma(Stage3MArgs a) {
+    using S = TetM<P>;
+    constexpr int Np = S::Np, NF4 = S::NF4, KV = S::KV, KS = S::KS, KP = S::KP, KPP = S::KPP, MT = S::MT;
+    constexpr int W = S::W, NTH = S::NTH, NT = S::NT, EB = S::EB, NG4 = S::NG4, TPT = S::TPT;
+    constexpr int NV4 = (EB * kF3 * Np / 4 + NTH - 1) / NTH;   // float4 of a full tile per thread
+    static_assert(EB * kF3 * Np % 4 == 0, "a full tile is whole float4");
+    __shared__ __attribute__((aligned(16))) float sB[NT][16][KPP];   // B operand (column-major); then the result
+    __shared__ __attribute__((aligned(16))) float sU[EB * kF3 * Np];  // read and written as float4
+    __shared__ float sG[EB * kGeo3];
+    __shared__ int sFM[NF4];
+    const long k0 = (long)blockIdx.x * EB;
+    const int nel = (int)min((long)EB, (long)a.K - k0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long base = k0 * kF3 * Np;   // a multiple of 4 floats: EB is a multiple of 12
+    const int nflt = nel * kF3 * Np;
+    const int n4 = nflt / 4;            // whole float4 of this tile (the rest: scalar tail)
+    const int ntask = nel * NF4;
+
+    // ---- loads: the tile and its geometry, then the neighbour traces of
+    // this thread's face-node tasks (task = element * 4 Nfp + face node;
+    // addresses clamped into the tile, a wall task reads its own element and
+    // ignores it), which stay in flight across the barrier and the
+    // pointwise phase
+    const f32x4_t *U4 = reinterpret_cast<const f32x4_t *>(a.Uin + base);
+#pragma unroll
+    for (int v = 0; v < NV4; ++v) {
+        const int z = tid + v * NTH;
+        if (z < n4) reinterpret_cast<f32x4_t *>(sU)[z] = U4[z];
+    }
+    for (int z = 4 * n4 + tid; z < nflt; z += NTH) sU[z] = a.Uin[base + z];
+    for (int z = tid; z < nel * kGeo3; z += NTH) sG[z] = a.geo[k0 * kGeo3 + z];
+    for (int z = tid; z < NF4; z += NTH) sFM[z] = a.fmask[z];
+    int nbv[TPT];
+    float upn[TPT][kF3];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const int task = min(tid + t * NTH, ntask - 1);
+        const int e = task / NF4, q = task - e * NF4;
+        nbv[t] = a.fmap[(k0 + e) * NF4 + q];
+        const long src = nbv[t] >= 0 ? (long)nbv[t] : (k0 + e) * kF3 * Np;
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) upn[t][c] = a.Uin[src + c * Np];
+    }
+    if constexpr (KP > KV) {
+        // the contraction's padding rows: zero (the A operand is zero there,
+        // and 0 x garbage could be NaN)
+        constexpr int PADR = KP - KV, PADN = 16 * PADR;
+        for (int z = tid; z < NT * PADN; z += NTH) {
+            const int t = z / PADN, rem = z - t * PADN;
+            sB[t][rem / PADR][KV + rem % PADR] = 0.f;
+        }
+    }
+    __syncthreads();
+
+    // ---- pointwise contravariant fluxes: row d Np + i of column 5 (el % 3) + c
+    for (int z = tid; z < nel * Np; z += NTH) {
+        const int el = z / Np, i = z - el * Np;
+        float u[kF3], F[kF3], G[kF3], H[kF3];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
+        euler3_flux(a.g, u, F, G, H);
+        const float *m = sG + el * kGeo3;
+        float(*B)[KPP] = sB[el / 3];
+        const int col = (el % 3) * kF3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+#pragma unroll
+            for (int c = 0; c < kF3; ++c) B[col + c][d * Np + i] = m0 * F[c] + m1 * G[c] + m2 * H[c];
+        }
+    }
+    // ---- face terms: row 3 Np + q
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const int task = tid + t * NTH;
+        if (task < ntask) {
+            const int e = task / NF4, q = task - e * NF4, f = q / (NF4 / 4);
+            const int vm = sFM[q];
+            const float *gm = sG + e * kGeo3;
+            const float nx = gm[9 + 3 * f], ny = gm[10 + 3 * f], nz = gm[11 + 3 * f], fs = gm[21 + f];
+            float um[kF3], up[kF3];
+#pragma unroll
+            for (int c = 0; c < kF3; ++c) um[c] = sU[(e * kF3 + c) * Np + vm];
+            if (nbv[t] >= 0) {
+#pragma unroll
+                for (int c = 0; c < kF3; ++c) up[c] = upn[t][c];
+            } else {
+                const float mn = um[1] * nx + um[2] * ny + um[3] * nz;
+                up[0] = um[0];
+                up[1] = um[1] - 2.f * mn * nx;
+                up[2] = um[2] - 2.f * mn * ny;
+                up[3] = um[3] - 2.f * mn * nz;
+                up[4] = um[4];
+            }
+            float fm[kF3], fp[kF3], lm, lp;
+            normal_flux3(a.g, um, nx, ny, nz, fm, lm);
+            normal_flux3(a.g, up, nx, ny, nz, fp, lp);
+            const float lam = lm > lp ? lm : lp;
+            float(*B)[KPP] = sB[e / 3];
+            const int col = (e % 3) * kF3;
+#pragma unroll
+            for (int c = 0; c < kF3; ++c)
+                B[col + c][3 * Np + q] = fs * (0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]));
+        }
+    }
+    // the A operand (the same for every block, so it comes from the caches)
+    // and the Runge-Kutta register, requested before the barrier so that
+    // their latency overlaps the other wavefronts' flux work and the product
+    f32x4_t ga4[NG4];
+#pragma unroll
+    for (int g = 0; g < NG4; ++g) ga4[g] = a.opsA[g * 64 + lane];
+    f32x4_t r4[NV4];
+    const bool rk_read = a.mode && a.stage > 0;
+#pragma unroll
+    for (int v = 0; v < NV4; ++v) {
+        const int z = min(tid + v * NTH, n4 - 1);
+        r4[v] = rk_read && n4 > 0 ? reinterpret_cast<const f32x4_t *>(a.R + base)[z] : f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();
+
+    // ---- the product: wave w takes column groups w, w + W, ...; result row
+    // = node, column = 5 (element % 3) + field, written over the group's own
+    // (fully read) B block as [element % 3][field][node]
+    for (int t = wave; t < NT; t += W) {
+        if (3 * t >= nel) break;
+        f32x4_t acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float b = sB[t][lane & 15][4 * ks + (lane >> 4)];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int z = ks * MT + mt;
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga4[z / 4][z % 4], b, acc[mt], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int col = lane & 15, le = col / kF3, c = col - le * kF3;
+        if (col < 15 && 3 * t + le < nel) {
+            float *res = &sB[t][0][0];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * mt + 4 * (lane >> 4) + r;
+                    if (i < Np) res[(le * kF3 + c) * Np + i] = acc[mt][r];
+                }
+        }
+    }
+    __syncthreads();
+
+    // ---- epilogue: Runge-Kutta update (or the bare rhs), float4 where the
+    // tile is whole float4 (result element el / 3 block, offset within it)
+    const float dt = a.mode ? float(*a.dt) : 0.f;
+    auto result = [&](int z) -> float {
+        const int el = z / (kF3 * Np), off = z - el * (kF3 * Np);
+        return (&sB[el / 3][0][0])[(el % 3) * kF3 * Np + off];
+    };
+#pragma unroll
+    for (int v = 0; v < NV4; ++v) {
+        const int z4 = tid + v * NTH;
+        if (z4 < n4) {
+            const int z = 4 * z4;
+            const f32x4_t rh = {result(z), result(z + 1), result(z + 2), result(z + 3)};
+            if (a.mode == 0) {
+                reinterpret_cast<f32x4_t *>(a.rhs + base)[z4] = rh;
+            } else {
+                const f32x4_t rr = a.stage == 0 ? dt * rh : a.ra * r4[v] + dt * rh;
+                reinterpret_cast<f32x4_t *>(a.R + base)[z4] = rr;
+                reinterpret_cast<f32x4_t *>(a.Uout + base)[z4] = reinterpret_cast<const f32x4_t *>(sU)[z4] + a.rb * rr;
+            }
+        }
+    }
+    for (int z = 4 * n4 + tid; z < nflt; z += NTH) {
+        const float rh = result(z);
+        const long idx = base + z;
+        if (a.mode == 0) {
+            a.rhs[idx] = rh;
+        } else {
+            const float rr = a.stage == 0 ? dt * rh : a.ra * a.R[idx] + dt * rh;
+            a.R[idx] = rr;
+            a.Uout[idx] = sU[z] + a.rb * rr;
+        }
+    }
+}
+
 // Time-step bound in FP64 at every face node: (P+1)^2 Fscale (|v| + c) / 2,
-// maximum per block into *vmax (non-negative doubles order like their bit
-// patterns); the state check (non-finite, rho <= 0, p <= 0) at every face
-// node.
+// maximum per block into one of kSlots3 slots (block id mod kSlots3, so that
+// the atomics of thousands of blocks do not queue on one address;
+// non-negative doubles order like their bit patterns); the state check
+// (non-finite, rho <= 0, p <= 0) at every face node.
 template <typename T, int P>
 __global__ __launch_bounds__(kB3) void k_cfl3(int K, double g, const T *__restrict__ U, const T *__restrict__ geo,
                                              const int *__restrict__ fmask, unsigned long long *vmax,
@@ -211,22 +456,28 @@ __global__ __launch_bounds__(kB3) void k_cfl3(int K, double g, const T *__restri
     if (threadIdx.x == 0) {
         double m = sRed[0];
         for (int w = 1; w < kB3 / 64; ++w) m = sRed[w] > m ? sRed[w] : m;
-        atomicMax(vmax, (unsigned long long)__double_as_longlong(m));
+        atomicMax(vmax + (blockIdx.x & (kSlots3 - 1)), (unsigned long long)__double_as_longlong(m));
     }
 }
 
 // dt = CFL / bound (or the fixed step), booked into the scalars; clears the
-// bound for the next step.
+// slots for the next step.  One wavefront of kSlots3 lanes.
 __global__ void k_dt3(double cfl, double dt_fixed, unsigned long long *vmax, double *scal) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double b = __longlong_as_double((long long)*vmax);
+    const int l = threadIdx.x;
+    unsigned long long v = vmax[l];
+    for (int off = kSlots3 / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    vmax[l] = 0ull;
+    if (l != 0) return;
+    const double b = __longlong_as_double((long long)v);
     const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / b;
     scal[S_DT] = dt;
     scal[S_T] += dt;
     scal[S_DTMIN] = dt < scal[S_DTMIN] ? dt : scal[S_DTMIN];
     scal[S_DTMAX] = dt > scal[S_DTMAX] ? dt : scal[S_DTMAX];
     scal[S_STEPS] += 1.0;
-    *vmax = 0ull;
 }
 
 // Straight-element geometry in FP64: metric terms from the vertex
@@ -272,10 +523,11 @@ __global__ void k_geometry3(int K, const double *__restrict__ X, double *__restr
 }
 
 __global__ void k_reset3(double *scal, unsigned long long *vmax, int *flag) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int l = threadIdx.x;
+    vmax[l] = 0ull;
+    if (l != 0) return;
     for (int i = 0; i < S_NSCAL; ++i) scal[i] = 0.0;
     scal[S_DTMIN] = __longlong_as_double(0x7ff0000000000000ll);   // +inf
-    *vmax = 0ull;
     *flag = 0;
 }
 
@@ -300,13 +552,76 @@ int tet3_blocks(int K, int P, bool fp32) {
 }
 
 hipError_t launch_reset3(const Tet3Mesh &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_reset3, dim3(1), dim3(64), 0, st, m.scal, m.vmax, m.flag);
+    hipLaunchKernelGGL(k_reset3, dim3(1), dim3(kSlots3), 0, st, m.scal, m.vmax, m.flag);
     return hipGetLastError();
 }
 
 hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hipStream_t st) {
     hipLaunchKernelGGL(k_geometry3, dim3((K + 127) / 128), dim3(128), 0, st, K, X, geo, count);
     return hipGetLastError();
+}
+
+size_t tet3_mfma_opsA_floats(int P) {
+    return with_order3(P, [](auto PC) {
+        using S = TetM<decltype(PC)::value>;
+        return size_t(S::NG4) * 64 * 4;
+    });
+}
+
+void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                         float *out) {
+    with_order3(P, [&](auto PC) {
+        using S = TetM<decltype(PC)::value>;
+        constexpr int Np = S::Np, NF4 = S::NF4;
+        std::fill(out, out + size_t(S::NG4) * 64 * 4, 0.f);
+        for (int ks = 0; ks < S::KS; ++ks)
+            for (int mt = 0; mt < S::MT; ++mt)
+                for (int l = 0; l < 64; ++l) {
+                    const int m = 16 * mt + (l & 15), k = 4 * ks + (l >> 4);
+                    double v = 0.0;
+                    if (m < Np) {
+                        if (k < Np)
+                            v = -Dr[m * Np + k];
+                        else if (k < 2 * Np)
+                            v = -Ds[m * Np + (k - Np)];
+                        else if (k < 3 * Np)
+                            v = -Dt[m * Np + (k - 2 * Np)];
+                        else if (k < S::KV)
+                            v = LIFT[m * NF4 + (k - 3 * Np)];
+                    }
+                    // lane l's fragment z = ks MT + mt, four per 16-byte group
+                    const int z = ks * S::MT + mt;
+                    out[(size_t(z / 4) * 64 + l) * 4 + z % 4] = float(v);
+                }
+        return 0;
+    });
+}
+
+static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                              hipStream_t st) {
+    Stage3MArgs a;
+    a.K = m.K;
+    a.stage = stage;
+    a.mode = rhs ? 0 : 1;
+    a.g = float(m.gamma);
+    a.ra = float(rk_a(stage));
+    a.rb = float(rk_b(stage));
+    a.Uin = static_cast<const float *>(Uin);
+    a.Uout = static_cast<float *>(Uout);
+    a.R = static_cast<float *>(R);
+    a.rhs = static_cast<float *>(rhs);
+    a.geo = m.geo32;
+    a.fmap = m.fmap;
+    a.fmask = m.fmask;
+    a.opsA = reinterpret_cast<const f32x4_t *>(m.opsA);
+    a.dt = m.scal + S_DT;
+    return with_order3(m.P, [&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        using S = TetM<P>;
+        const int blocks = (m.K + S::EB - 1) / S::EB;
+        hipLaunchKernelGGL((k_stage3_mfma<P>), dim3(blocks), dim3(S::NTH), 0, st, a);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -337,6 +652,7 @@ static hipError_t stage3_t(const Tet3Mesh &m, const void *Uin, void *Uout, void 
 
 hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                          hipStream_t st) {
+    if (m.fp32 && m.opsA) return stage3_mfma(m, Uin, Uout, R, rhs, stage, st);
     return m.fp32 ? stage3_t<float>(m, Uin, Uout, R, rhs, stage, st)
                   : stage3_t<double>(m, Uin, Uout, R, rhs, stage, st);
 }
@@ -354,7 +670,7 @@ hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStr
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dt3, dim3(1), dim3(64), 0, st, m.cfl, dt_fixed, m.vmax, m.scal);
+    hipLaunchKernelGGL(k_dt3, dim3(1), dim3(kSlots3), 0, st, m.cfl, dt_fixed, m.vmax, m.scal);
     return hipGetLastError();
 }
 
