@@ -63,13 +63,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(precision="fp32", av=False):
+def kernel_source_hash(precision="fp32", av=False, workload=None):
     """Hash of the sources of the stage's kernels for this precision (with
-    artificial viscosity the sensor and gradient kernels too)."""
+    artificial viscosity the sensor and gradient kernels too; the 3D
+    workload's in their own file)."""
     h = hashlib.sha256()
     files = ("kernels.hip", "common.hpp") if precision == "fp64" else ("stage_mfma.hip", "common.hpp")
     if av and precision != "fp64":
         files += ("kernels.hip",)
+    if workload == "tet3d":
+        files = ("tet3d.hip", "common.hpp")
     for f in files:
         with open(os.path.join(ROOT, "paper_1208_4772_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -143,7 +146,7 @@ def load_traffic(workload, precision, launch_bytes, av=False):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_hash") != kernel_source_hash(precision, av):
+    if t.get("kernel_source_hash") != kernel_source_hash(precision, av, workload):
         return None
     return t.get("bytes_per_launch")
 
@@ -283,7 +286,8 @@ def bench_tet3d(args, dev):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOADS["tet3d"], "K": grid.K, "P": 4, "dof": dofs, "precision": "fp32"},
         "roofline": dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_stage3<float,4>",
+                         frac=round(achieved / HBM_PEAK_GBS, 4),
+                         traffic=load_traffic("tet3d", "fp32", launch_bytes), kernel="k_stage3_mfma<4>",
                          avg_launch_us=round(avg_s * 1e6, 3), launches=5 * steps,
                          algorithmic_bytes_per_launch=int(launch_bytes),
                          note="average over the stage launches of the timed region, the per-step "

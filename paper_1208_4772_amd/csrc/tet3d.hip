@@ -23,11 +23,13 @@
 // field is one product
 //   rhs = [-Dr  -Ds  -Dt  LIFT] (Np x (3 Np + 4 Nfp)) . [F_r; F_s; F_t; Fscale (n.F - F*)],
 // formed for column groups of 3 elements x 5 fields (15 of 16 columns) with
-// v_mfma_f32_16x16x4f32; the A operand (the same few tens of KB for every
-// block) is read from the caches, the B operand is built in LDS.
+// v_mfma_f32_16x16x4f32, in four passes (faces, then r, s, t) that share one
+// B buffer in LDS; the A operand of each pass (the same for every block) is
+// read from the caches into registers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -181,31 +183,38 @@ __global__ __launch_bounds__(kB3) void k_stage3(Stage3Args<T> a) {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// Shape of the matrix-core stage: contraction length KV = 3 Np + 4 Nfp in
-// KS k-steps of 4, MT 16-row output tiles, NT column groups (3 elements
-// each) per 4-wave block, as many as keep the block's LDS near 48 KB.  The
-// B operand is stored column-major with a column stride KPP = 4 (mod 8)
-// words: the flux writes (consecutive rows) and the fragment reads (16
-// columns x 4 rows) then spread over the LDS banks.
+// Shape of the matrix-core stage, in four passes over one small B buffer:
+// the face terms (LIFT, 4 Nfp rows), then the contravariant fluxes along
+// r, s and t (Dr, Ds, Dt, Np rows each, padded to whole k-steps).  Small
+// LDS per element keeps several blocks on a CU to hide memory latency (at
+// P = 4: 25 KB and 91 registers, five blocks per CU; one pass over a
+// 3 Np + 4 Nfp row buffer took 53 KB and 166 registers, three blocks, and
+// 33% more time).  The B operand is stored column-major with a column
+// stride KPP = 4 (mod 8) words: the flux writes (consecutive rows) and the
+// fragment reads (16 columns x 4 rows) then spread over the LDS banks.
 template <int P>
 struct TetM {
     static constexpr int Np = (P + 1) * (P + 2) * (P + 3) / 6;
     static constexpr int Nfp = (P + 1) * (P + 2) / 2;
     static constexpr int NF4 = 4 * Nfp;
-    static constexpr int KV = 3 * Np + NF4;
-    static constexpr int KS = (KV + 3) / 4;
-    static constexpr int KP = 4 * KS;
-    static constexpr int KPP = KP % 8 == 4 ? KP : KP + 4;
+    static constexpr int KSD = (Np + 3) / 4;       // k-steps of one direction
+    static constexpr int KSL = NF4 / 4;            // k-steps of the face pass
+    static constexpr int KB = 4 * KSD > NF4 ? 4 * KSD : NF4;
+    static constexpr int KPP = KB % 8 == 4 ? KB : KB + 4;
     static constexpr int MT = (Np + 15) / 16;
-    static constexpr int NZ = KS * MT;            // A fragments per lane
-    static constexpr int NG4 = (NZ + 3) / 4;      // ... in 16-byte groups
+    static constexpr int NZD = KSD * MT, NGD = (NZD + 3) / 4;
+    static constexpr int NZL = KSL * MT, NGL = (NZL + 3) / 4;
     static constexpr int W = 4;
     static constexpr int NTH = 64 * W;
-    static constexpr int group_bytes = (16 * KPP + 3 * kF3 * Np) * 4;
-    static constexpr int nt_fit = (48 * 1024 / group_bytes) / W * W;
-    static constexpr int NT = nt_fit < W ? W : (nt_fit > 16 ? 16 : nt_fit);
+    // one column group per wavefront: measured on 26,112 tetrahedra, 8, 12
+    // or 16 groups per block are 8-100% slower at every order (fewer blocks
+    // per CU to hide the memory latency)
+    static constexpr int NT = W;
+    static constexpr int GW = NT / W;              // column groups per wavefront
     static constexpr int EB = 3 * NT;
     static constexpr int TPT = (EB * NF4 + NTH - 1) / NTH;   // face-node tasks per thread
+    static constexpr int PPT = (EB * Np + NTH - 1) / NTH;    // pointwise tasks per thread
+    static_assert(NF4 % 4 == 0, "face rows are whole k-steps");
     static_assert(15 * Np <= 16 * KPP, "a group's result fits in its B block");
 };
 
@@ -216,37 +225,35 @@ struct Stage3MArgs {
     float *__restrict__ Uout;
     float *__restrict__ R;
     float *__restrict__ rhs;
-    const float *__restrict__ geo;   // [K][25]
-    const int *__restrict__ fmap;    // [K][4 Nfp]
-    const int *__restrict__ fmask;   // [4 Nfp]
-    const f32x4_t *__restrict__ opsA;  // [NG4][64]: fragment z = ks MT + mt of lane l in group z / 4, slot z % 4
+    const float *__restrict__ geo;
+    const int *__restrict__ fmap;
+    const int *__restrict__ fmask;
+    const f32x4_t *__restrict__ opsA;  // [4][NG][64]: face, then r, s, t fragments (NG = max(NGL, NGD));
+                                       // lane l of fragment z = ks MT + mt: slot z % 4 of group z / 4
     const double *__restrict__ dt;
 };
 
 template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_stage3_mfma(Stage3MArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_stage3_mfma(Stage3MArgs a) {
     using S = TetM<P>;
-    constexpr int Np = S::Np, NF4 = S::NF4, KV = S::KV, KS = S::KS, KP = S::KP, KPP = S::KPP, MT = S::MT;
-    constexpr int W = S::W, NTH = S::NTH, NT = S::NT, EB = S::EB, NG4 = S::NG4, TPT = S::TPT;
-    constexpr int NV4 = (EB * kF3 * Np / 4 + NTH - 1) / NTH;   // float4 of a full tile per thread
+    constexpr int Np = S::Np, NF4 = S::NF4, KSD = S::KSD, KSL = S::KSL, KPP = S::KPP, MT = S::MT;
+    constexpr int W = S::W, NTH = S::NTH, NT = S::NT, GW = S::GW, EB = S::EB, NGD = S::NGD, NGL = S::NGL;
+    constexpr int TPT = S::TPT, PPT = S::PPT;
+    constexpr int NG = NGL > NGD ? NGL : NGD;
+    constexpr int NV4 = (EB * kF3 * Np / 4 + NTH - 1) / NTH;
     static_assert(EB * kF3 * Np % 4 == 0, "a full tile is whole float4");
-    __shared__ __attribute__((aligned(16))) float sB[NT][16][KPP];   // B operand (column-major); then the result
-    __shared__ __attribute__((aligned(16))) float sU[EB * kF3 * Np];  // read and written as float4
+    __shared__ __attribute__((aligned(16))) float sB[NT][16][KPP];
+    __shared__ __attribute__((aligned(16))) float sU[EB * kF3 * Np];
     __shared__ float sG[EB * kGeo3];
     __shared__ int sFM[NF4];
     const long k0 = (long)blockIdx.x * EB;
     const int nel = (int)min((long)EB, (long)a.K - k0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long base = k0 * kF3 * Np;   // a multiple of 4 floats: EB is a multiple of 12
+    const long base = k0 * kF3 * Np;
     const int nflt = nel * kF3 * Np;
-    const int n4 = nflt / 4;            // whole float4 of this tile (the rest: scalar tail)
+    const int n4 = nflt / 4;
     const int ntask = nel * NF4;
 
-    // ---- loads: the tile and its geometry, then the neighbour traces of
-    // this thread's face-node tasks (task = element * 4 Nfp + face node;
-    // addresses clamped into the tile, a wall task reads its own element and
-    // ignores it), which stay in flight across the barrier and the
-    // pointwise phase
     const f32x4_t *U4 = reinterpret_cast<const f32x4_t *>(a.Uin + base);
 #pragma unroll
     for (int v = 0; v < NV4; ++v) {
@@ -267,35 +274,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
         for (int c = 0; c < kF3; ++c) upn[t][c] = a.Uin[src + c * Np];
     }
-    if constexpr (KP > KV) {
-        // the contraction's padding rows: zero (the A operand is zero there,
-        // and 0 x garbage could be NaN)
-        constexpr int PADR = KP - KV, PADN = 16 * PADR;
-        for (int z = tid; z < NT * PADN; z += NTH) {
-            const int t = z / PADN, rem = z - t * PADN;
-            sB[t][rem / PADR][KV + rem % PADR] = 0.f;
-        }
-    }
     __syncthreads();
 
-    // ---- pointwise contravariant fluxes: row d Np + i of column 5 (el % 3) + c
-    for (int z = tid; z < nel * Np; z += NTH) {
-        const int el = z / Np, i = z - el * Np;
-        float u[kF3], F[kF3], G[kF3], H[kF3];
+    // one pass of the product: B rows [0, 4 ks_count) of every group this
+    // wavefront owns, against A fragments ga (fragment z = ks MT + mt)
+    f32x4_t acc[GW][MT];
 #pragma unroll
-        for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
-        euler3_flux(a.g, u, F, G, H);
-        const float *m = sG + el * kGeo3;
-        float(*B)[KPP] = sB[el / 3];
-        const int col = (el % 3) * kF3;
+    for (int gi = 0; gi < GW; ++gi)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+        for (int mt = 0; mt < MT; ++mt) acc[gi][mt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    auto product = [&](const f32x4_t(&ga)[NG], auto KSC) {
+        constexpr int KSN = decltype(KSC)::value;
 #pragma unroll
-            for (int c = 0; c < kF3; ++c) B[col + c][d * Np + i] = m0 * F[c] + m1 * G[c] + m2 * H[c];
+        for (int gi = 0; gi < GW; ++gi) {
+            const int t = wave + gi * W;
+            if (3 * t < nel) {
+#pragma unroll
+                for (int ks = 0; ks < KSN; ++ks) {
+                    const float b = sB[t][lane & 15][4 * ks + (lane >> 4)];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const int z = ks * MT + mt;
+                        acc[gi][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[z / 4][z % 4], b, acc[gi][mt], 0, 0, 0);
+                    }
+                }
+            }
         }
-    }
-    // ---- face terms: row 3 Np + q
+    };
+    f32x4_t ga[NG];
+
+    // ---- face terms: rows q < 4 Nfp
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
         const int task = tid + t * NTH;
@@ -325,16 +333,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             float(*B)[KPP] = sB[e / 3];
             const int col = (e % 3) * kF3;
 #pragma unroll
-            for (int c = 0; c < kF3; ++c)
-                B[col + c][3 * Np + q] = fs * (0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]));
+            for (int c = 0; c < kF3; ++c) B[col + c][q] = fs * (0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]));
         }
     }
-    // the A operand (the same for every block, so it comes from the caches)
-    // and the Runge-Kutta register, requested before the barrier so that
-    // their latency overlaps the other wavefronts' flux work and the product
-    f32x4_t ga4[NG4];
 #pragma unroll
-    for (int g = 0; g < NG4; ++g) ga4[g] = a.opsA[g * 64 + lane];
+    for (int g = 0; g < NG; ++g) ga[g] = a.opsA[g * 64 + lane];
+    // the pointwise fluxes of this thread's nodes, kept in registers for the
+    // three direction passes
+    float Fx[PPT][kF3], Fy[PPT][kF3], Fz[PPT][kF3];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int z = min(tid + p * NTH, nel * Np - 1);
+        const int el = z / Np, i = z - el * Np;
+        float u[kF3];
+#pragma unroll
+        for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
+        euler3_flux(a.g, u, Fx[p], Fy[p], Fz[p]);
+    }
+    __syncthreads();
+    product(ga, std::integral_constant<int, KSL>());
+
+    // ---- the three directions: rows i < Np (rows Np .. 4 KSD zero)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        __syncthreads();
+        if constexpr (4 * KSD > Np) {
+            constexpr int PADR = 4 * KSD - Np, PADN = 16 * PADR;
+            for (int z = tid; z < NT * PADN; z += NTH) {
+                const int t = z / PADN, rem = z - t * PADN;
+                sB[t][rem / PADR][Np + rem % PADR] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int z = tid + p * NTH;
+            if (z < nel * Np) {
+                const int el = z / Np, i = z - el * Np;
+                const float *m = sG + el * kGeo3 + 3 * d;
+                const float m0 = m[0], m1 = m[1], m2 = m[2];
+                float(*B)[KPP] = sB[el / 3];
+                const int col = (el % 3) * kF3;
+#pragma unroll
+                for (int c = 0; c < kF3; ++c) B[col + c][i] = m0 * Fx[p][c] + m1 * Fy[p][c] + m2 * Fz[p][c];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) ga[g] = a.opsA[((1 + d) * NG + g) * 64 + lane];
+        __syncthreads();
+        product(ga, std::integral_constant<int, KSD>());
+    }
     f32x4_t r4[NV4];
     const bool rk_read = a.mode && a.stage > 0;
 #pragma unroll
@@ -343,26 +390,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         r4[v] = rk_read && n4 > 0 ? reinterpret_cast<const f32x4_t *>(a.R + base)[z] : f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
     __syncthreads();
-
-    // ---- the product: wave w takes column groups w, w + W, ...; result row
-    // = node, column = 5 (element % 3) + field, written over the group's own
-    // (fully read) B block as [element % 3][field][node]
-    for (int t = wave; t < NT; t += W) {
-        if (3 * t >= nel) break;
-        f32x4_t acc[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float b = sB[t][lane & 15][4 * ks + (lane >> 4)];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const int z = ks * MT + mt;
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga4[z / 4][z % 4], b, acc[mt], 0, 0, 0);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    for (int gi = 0; gi < GW; ++gi) {
+        const int t = wave + gi * W;
         const int col = lane & 15, le = col / kF3, c = col - le * kF3;
         if (col < 15 && 3 * t + le < nel) {
             float *res = &sB[t][0][0];
@@ -371,14 +401,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * mt + 4 * (lane >> 4) + r;
-                    if (i < Np) res[(le * kF3 + c) * Np + i] = acc[mt][r];
+                    if (i < Np) res[(le * kF3 + c) * Np + i] = acc[gi][mt][r];
                 }
         }
     }
     __syncthreads();
 
-    // ---- epilogue: Runge-Kutta update (or the bare rhs), float4 where the
-    // tile is whole float4 (result element el / 3 block, offset within it)
     const float dt = a.mode ? float(*a.dt) : 0.f;
     auto result = [&](int z) -> float {
         const int el = z / (kF3 * Np), off = z - el * (kF3 * Np);
@@ -561,38 +589,41 @@ hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hip
     return hipGetLastError();
 }
 
+template <int P>
+constexpr int tet3_ng() {
+    using S = TetM<P>;
+    return S::NGL > S::NGD ? S::NGL : S::NGD;
+}
+
 size_t tet3_mfma_opsA_floats(int P) {
-    return with_order3(P, [](auto PC) {
-        using S = TetM<decltype(PC)::value>;
-        return size_t(S::NG4) * 64 * 4;
-    });
+    return with_order3(P, [](auto PC) { return size_t(4) * tet3_ng<decltype(PC)::value>() * 64 * 4; });
 }
 
 void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
                          float *out) {
     with_order3(P, [&](auto PC) {
-        using S = TetM<decltype(PC)::value>;
-        constexpr int Np = S::Np, NF4 = S::NF4;
-        std::fill(out, out + size_t(S::NG4) * 64 * 4, 0.f);
-        for (int ks = 0; ks < S::KS; ++ks)
-            for (int mt = 0; mt < S::MT; ++mt)
-                for (int l = 0; l < 64; ++l) {
-                    const int m = 16 * mt + (l & 15), k = 4 * ks + (l >> 4);
-                    double v = 0.0;
-                    if (m < Np) {
-                        if (k < Np)
-                            v = -Dr[m * Np + k];
-                        else if (k < 2 * Np)
-                            v = -Ds[m * Np + (k - Np)];
-                        else if (k < 3 * Np)
-                            v = -Dt[m * Np + (k - 2 * Np)];
-                        else if (k < S::KV)
-                            v = LIFT[m * NF4 + (k - 3 * Np)];
+        constexpr int PP = decltype(PC)::value;
+        using S = TetM<PP>;
+        constexpr int Np = S::Np, NF4 = S::NF4, MT = S::MT, NG = tet3_ng<PP>();
+        std::fill(out, out + size_t(4) * NG * 64 * 4, 0.f);
+        const double *D[3] = {Dr, Ds, Dt};
+        for (int pass = 0; pass < 4; ++pass) {
+            const int ksn = pass == 0 ? S::KSL : S::KSD;
+            for (int mt = 0; mt < MT; ++mt)
+                for (int l = 0; l < 64; ++l)
+                    for (int ks = 0; ks < ksn; ++ks) {
+                        const int m = 16 * mt + (l & 15), k = 4 * ks + (l >> 4);
+                        double v = 0.0;
+                        if (m < Np) {
+                            if (pass == 0)
+                                v = LIFT[m * NF4 + k];
+                            else if (k < Np)
+                                v = -D[pass - 1][m * Np + k];
+                        }
+                        const int z = ks * MT + mt;
+                        out[((size_t(pass) * NG + z / 4) * 64 + l) * 4 + z % 4] = float(v);
                     }
-                    // lane l's fragment z = ks MT + mt, four per 16-byte group
-                    const int z = ks * S::MT + mt;
-                    out[(size_t(z / 4) * 64 + l) * 4 + z % 4] = float(v);
-                }
+        }
         return 0;
     });
 }
