@@ -83,7 +83,8 @@ int dg3_mesh_setup(const dg3_mesh_desc *desc, void *stream, dg3_mesh **out);
 int dg3_mesh_destroy(dg3_mesh *mesh);
 
 /* Bytes of one state array and of the work buffer dg3_run needs (the
- * Runge-Kutta register and two stage buffers). */
+ * Runge-Kutta register and two stage buffers, each starting on a 256-byte
+ * boundary of the work buffer). */
 int dg3_buffer_bytes(const dg3_mesh *mesh, size_t *state_bytes, size_t *work_bytes);
 
 /* rhs = dU/dt of the device state U (no time stepping).  Enqueues only.

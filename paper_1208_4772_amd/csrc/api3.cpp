@@ -349,6 +349,9 @@ struct dg3_mesh {
         return DG_OK;
     }
     size_t state_bytes() const { return size_t(m.K) * 5 * m.Np * (m.fp32 ? 4 : 8); }
+    // offset of each buffer in the work area: the stage kernels move whole
+    // tiles as 16-byte vectors, so every buffer starts 256-byte aligned
+    size_t slot_bytes() const { return (state_bytes() + 255) / 256 * 256; }
     ~dg3_mesh() {
         if (done) (void)hipEventDestroy(done);
         for (void *p : allocs) (void)hipFree(p);
@@ -423,29 +426,15 @@ int dg3_mesh_setup(const dg3_mesh_desc *d, void *stream, dg3_mesh **out) {
     m.gamma = d->gamma;
     m.cfl = d->cfl;
     int rc;
-    double *X_d, *geo64, *ops64, *scal;
+    double *X_d, *geo64, *scal;
     int *fmap_d, *fmask_d, *count_d, *flag_d;
     unsigned long long *vmax_d;
-    const size_t nops = size_t(3) * Np * Np + size_t(Np) * NF4;
     if ((rc = h->alloc(&X_d, size_t(K) * 12)) || (rc = h->alloc(&geo64, size_t(K) * 25)) ||
-        (rc = h->alloc(&ops64, nops)) || (rc = h->alloc(&fmap_d, fmap.size())) ||
-        (rc = h->alloc(&fmask_d, size_t(NF4))) || (rc = h->alloc(&count_d, 1)) || (rc = h->alloc(&flag_d, 1)) ||
-        (rc = h->alloc(&scal, S_NSCAL)) || (rc = h->alloc(&vmax_d, kSlots3)))
+        (rc = h->alloc(&fmap_d, fmap.size())) || (rc = h->alloc(&fmask_d, size_t(NF4))) ||
+        (rc = h->alloc(&count_d, 1)) || (rc = h->alloc(&flag_d, 1)) || (rc = h->alloc(&scal, S_NSCAL)) ||
+        (rc = h->alloc(&vmax_d, kSlots3)))
         return cleanup(rc);
-    // device operators column-major (Dr^T | Ds^T | Dt^T | LIFT^T): for a
-    // fixed column the threads of an element (one per row) read consecutive
-    // words
-    std::vector<double> ops(nops);
-    for (int j = 0; j < Np; ++j)
-        for (int i = 0; i < Np; ++i) {
-            ops[size_t(j) * Np + i] = o.Dr[size_t(i) * Np + j];
-            ops[size_t(Np) * Np + size_t(j) * Np + i] = o.Ds[size_t(i) * Np + j];
-            ops[size_t(2) * Np * Np + size_t(j) * Np + i] = o.Dt[size_t(i) * Np + j];
-        }
-    for (int m = 0; m < NF4; ++m)
-        for (int i = 0; i < Np; ++i) ops[size_t(3) * Np * Np + size_t(m) * Np + i] = o.LIFT[size_t(i) * NF4 + m];
     SETUP3(hipMemcpyAsync(X_d, d->X, sizeof(double) * size_t(K) * 12, hipMemcpyHostToDevice, st));
-    SETUP3(hipMemcpyAsync(ops64, ops.data(), sizeof(double) * ops.size(), hipMemcpyHostToDevice, st));
     SETUP3(hipMemcpyAsync(fmap_d, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice, st));
     SETUP3(hipMemcpyAsync(fmask_d, o.fmask.data(), sizeof(int) * NF4, hipMemcpyHostToDevice, st));
     SETUP3(hipMemsetAsync(count_d, 0, sizeof(int), st));
@@ -455,26 +444,32 @@ int dg3_mesh_setup(const dg3_mesh_desc *d, void *stream, dg3_mesh **out) {
     SETUP3(hipStreamSynchronize(st));
     if (bad > 0) return cleanup(report_error(DG_EGEOM, std::to_string(bad) + " elements with volume <= 0"));
     m.geo64 = geo64;
-    m.ops64 = ops64;
     m.fmap = fmap_d;
     m.fmask = fmask_d;
     m.scal = scal;
     m.vmax = vmax_d;
     m.flag = flag_d;
+    // the matrix-core A operand in the handle's precision (host copies live
+    // until the stream is synchronised below)
+    const size_t nA = tet3_mfma_opsA_values(P);
+    std::vector<float> opsA32;
+    std::vector<double> opsA64;
     if (m.fp32) {
-        float *geo32, *ops32;
-        if ((rc = h->alloc(&geo32, size_t(K) * 25)) || (rc = h->alloc(&ops32, nops))) return cleanup(rc);
+        float *geo32, *opsA_d;
+        if ((rc = h->alloc(&geo32, size_t(K) * 25)) || (rc = h->alloc(&opsA_d, nA))) return cleanup(rc);
         SETUP3(launch_cast(geo64, geo32, size_t(K) * 25, st));
-        SETUP3(launch_cast(ops64, ops32, nops, st));
+        opsA32.resize(nA);
+        tet3_mfma_fill_opsA(P, o.Dr.data(), o.Ds.data(), o.Dt.data(), o.LIFT.data(), opsA32.data());
+        SETUP3(hipMemcpyAsync(opsA_d, opsA32.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
         m.geo32 = geo32;
-        m.ops32 = ops32;
-        float *opsA_d;
-        const size_t nA = tet3_mfma_opsA_floats(P);
-        if ((rc = h->alloc(&opsA_d, nA))) return cleanup(rc);
-        std::vector<float> opsA(nA);
-        tet3_mfma_fill_opsA(P, o.Dr.data(), o.Ds.data(), o.Dt.data(), o.LIFT.data(), opsA.data());
-        SETUP3(hipMemcpyAsync(opsA_d, opsA.data(), sizeof(float) * nA, hipMemcpyHostToDevice, st));
         m.opsA = opsA_d;
+    } else {
+        double *opsA_d;
+        if ((rc = h->alloc(&opsA_d, nA))) return cleanup(rc);
+        opsA64.resize(nA);
+        tet3_mfma_fill_opsA64(P, o.Dr.data(), o.Ds.data(), o.Dt.data(), o.LIFT.data(), opsA64.data());
+        SETUP3(hipMemcpyAsync(opsA_d, opsA64.data(), sizeof(double) * nA, hipMemcpyHostToDevice, st));
+        m.opsA64 = opsA_d;
     }
     SETUP3(launch_reset3(m, st));
     SETUP3(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
@@ -494,7 +489,7 @@ int dg3_mesh_destroy(dg3_mesh *h) {
 int dg3_buffer_bytes(const dg3_mesh *h, size_t *state_bytes, size_t *work_bytes) {
     if (!h) return report_error(DG_EINVAL, "mesh is NULL");
     if (state_bytes) *state_bytes = h->state_bytes();
-    if (work_bytes) *work_bytes = 3 * h->state_bytes();
+    if (work_bytes) *work_bytes = 3 * h->slot_bytes();
     return DG_OK;
 }
 
@@ -515,7 +510,7 @@ int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_ru
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Tet3Mesh &m = h->m;
     char *w = static_cast<char *>(work);
-    const size_t sb = h->state_bytes();
+    const size_t sb = h->slot_bytes();
     void *R = w, *A = w + sb, *B = w + 2 * sb;
     void *in[5] = {U, A, B, A, B};
     void *outp[5] = {A, B, A, B, U};

@@ -196,9 +196,8 @@ struct Tet3Mesh {
     double gamma = 1.4, cfl = 0.5;
     const double *geo64 = nullptr;   // [K][25]
     const float *geo32 = nullptr;
-    const double *ops64 = nullptr;   // Dr^T | Ds^T | Dt^T | LIFT^T (column-major)
-    const float *ops32 = nullptr;
-    const float *opsA = nullptr;     // FP32 matrix-core A operand (tet3_mfma_fill_opsA); null: VALU stage
+    const float *opsA = nullptr;     // FP32 handles: matrix-core A operand (tet3_mfma_fill_opsA)
+    const double *opsA64 = nullptr;  // FP64 handles: the same in FP64 (tet3_mfma_fill_opsA64)
     const int *fmap = nullptr;       // [K][4 Nfp]
     const int *fmask = nullptr;      // [4 Nfp]
     double *scal = nullptr;          // [S_NSCAL]
@@ -206,11 +205,13 @@ struct Tet3Mesh {
     int *flag = nullptr;
 };
 constexpr int kSlots3 = 64;   // one wavefront
-int tet3_blocks(int K, int P, bool fp32);
+int tet3_blocks(int K, int P);   // blocks of the time-step bound kernel
 // A operand of the FP32 matrix-core stage [-Dr -Ds -Dt LIFT] in lane order
-size_t tet3_mfma_opsA_floats(int P);
+size_t tet3_mfma_opsA_values(int P);
 void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
                          float *out);
+void tet3_mfma_fill_opsA64(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                           double *out);
 hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hipStream_t st);
 // zeroes the scalars (dt_min = +inf), the bound and the flag
 hipError_t launch_reset3(const Tet3Mesh &m, hipStream_t st);

@@ -9,23 +9,18 @@
 // equispaced nodes (the lattice (i, j, k)/P, r fastest).  A straight element
 // has constant metric terms, normals and Fscale per face: 25 numbers.
 //
-// One block holds up to floor(256 / Np) elements (fewer where their LDS
-// would pass 48 KB), one thread per node:
-// pointwise contravariant fluxes into LDS, the volume term from the
-// reference derivative matrices (global memory, cached), one thread per
-// face node for the flux jumps (neighbour traces gathered through a
-// precomputed node map), LIFT, and the low-storage Runge-Kutta update.
-// The time step is reduced in FP64 from the state (k_cfl3, k_dt3).
-//
-// FP32 handles run the stage on the matrix cores instead (k_stage3_mfma):
-// with constant metric terms the volume term folds into contravariant
-// fluxes, F_a = sum_d (d r_a / d x_d) F_d, and the whole right-hand side of a
-// field is one product
+// The stage runs on the matrix cores in both precisions (k_stage3_mfma,
+// FP32; k_stage3_mfma64, FP64): with constant metric terms the volume term
+// folds into contravariant fluxes, F_a = sum_d (d r_a / d x_d) F_d, and the
+// whole right-hand side of a field is one product
 //   rhs = [-Dr  -Ds  -Dt  LIFT] (Np x (3 Np + 4 Nfp)) . [F_r; F_s; F_t; Fscale (n.F - F*)],
 // formed for column groups of 3 elements x 5 fields (15 of 16 columns) with
-// v_mfma_f32_16x16x4f32, in four passes (faces, then r, s, t) that share one
-// B buffer in LDS; the A operand of each pass (the same for every block) is
-// read from the caches into registers.
+// v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64, in four passes (faces, then
+// r, s, t) that share one B buffer in LDS; the A operand of each pass (the
+// same for every block) is read from the caches into registers.  Face
+// terms: one thread per face node, the neighbour's trace gathered through a
+// precomputed node map, the mirror state at walls.  The time step is
+// reduced in FP64 from the state (k_cfl3, k_dt3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,31 +36,13 @@ constexpr int kF3 = 5;          // fields
 constexpr int kB3 = 256;        // threads per block
 constexpr int kGeo3 = 25;       // r_x r_y r_z s_x s_y s_z t_x t_y t_z | (n_x n_y n_z) x 4 | Fscale x 4
 
-// Elements per block: one thread per node, and at most 48 KB of LDS (the
-// tile, its contravariant fluxes, its face jumps and its geometry).
-template <typename T, int P>
-struct Tet {
-    static constexpr int Np = (P + 1) * (P + 2) * (P + 3) / 6;
+// Elements per block of the time-step bound kernel: about two face-node
+// tasks per thread.
+template <int P>
+struct Bound3 {
     static constexpr int Nfp = (P + 1) * (P + 2) / 2;
     static constexpr int NF4 = 4 * Nfp;
-    static constexpr int per = (kF3 * Np + 3 * kF3 * Np + kF3 * NF4 + kGeo3) * int(sizeof(T));
-    static constexpr int by_lds = (48 * 1024) / per;
-    static constexpr int EB = (kB3 / Np) < by_lds ? (kB3 / Np) : by_lds;
-};
-
-template <typename T>
-struct Stage3Args {
-    int K, stage, mode;
-    T g, ra, rb;
-    const T *__restrict__ Uin;
-    T *__restrict__ Uout;
-    T *__restrict__ R;
-    T *__restrict__ rhs;
-    const T *__restrict__ geo;     // [K][25]
-    const int *__restrict__ fmap;  // [K][4 Nfp]: neighbour node base (kn*5*Np + node), -1 at a wall
-    const int *__restrict__ fmask; // [4 Nfp] face node -> volume node
-    const T *__restrict__ ops;     // Dr^T | Ds^T | Dt^T (Np x Np) | LIFT^T (4 Nfp x Np): column-major operators
-    const double *__restrict__ dt;
+    static constexpr int EB = 2 * kB3 / NF4;
 };
 
 template <typename T>
@@ -93,95 +70,32 @@ __device__ inline void normal_flux3(T g, const T u[kF3], T nx, T ny, T nz, T fn[
     lam = fabs(vn) + fsqrt(g * p * ir);
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(kB3) void k_stage3(Stage3Args<T> a) {
-    using S = Tet<T, P>;
-    constexpr int Np = S::Np, NF4 = S::NF4, EB = S::EB;
-    __shared__ T sU[EB][kF3][Np];
-    __shared__ T sC[EB][3][kF3][Np];     // contravariant fluxes along r, s, t
-    __shared__ T sJ[EB][kF3][NF4];       // Fscale (n.F(U-) - F*) at the face nodes
-    __shared__ T sG[EB][kGeo3];
-    const long k0 = (long)blockIdx.x * EB;
-    const int nel = (int)min((long)EB, (long)a.K - k0);
-    const int tid = threadIdx.x;
-    for (int z = tid; z < nel * kF3 * Np; z += kB3) (&sU[0][0][0])[z] = a.Uin[k0 * kF3 * Np + z];
-    for (int z = tid; z < nel * kGeo3; z += kB3) (&sG[0][0])[z] = a.geo[k0 * kGeo3 + z];
-    __syncthreads();
-
-    const int el = tid / Np, i = tid - el * Np;
-    const bool act = el < nel;
-    if (act) {
-        T u[kF3], F[kF3], G[kF3], H[kF3];
-#pragma unroll
-        for (int c = 0; c < kF3; ++c) u[c] = sU[el][c][i];
-        euler3_flux(a.g, u, F, G, H);
-        const T *m = sG[el];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int c = 0; c < kF3; ++c) sC[el][d][c][i] = m[3 * d] * F[c] + m[3 * d + 1] * G[c] + m[3 * d + 2] * H[c];
-    }
-    // face-node tasks: (element, face node)
-    for (int z = tid; z < nel * NF4; z += kB3) {
-        const int e = z / NF4, q = z - e * NF4, f = q / (NF4 / 4);
-        const long k = k0 + e;
-        const int vm = a.fmask[q];
-        T um[kF3], up[kF3];
-#pragma unroll
-        for (int c = 0; c < kF3; ++c) um[c] = sU[e][c][vm];
-        const T nx = sG[e][9 + 3 * f], ny = sG[e][10 + 3 * f], nz = sG[e][11 + 3 * f], fs = sG[e][21 + f];
-        const int base = a.fmap[k * NF4 + q];
-        if (base >= 0) {
-#pragma unroll
-            for (int c = 0; c < kF3; ++c) up[c] = a.Uin[(long)base + c * Np];
-        } else {
-            // slip wall: the mirror state
-            const T mn = um[1] * nx + um[2] * ny + um[3] * nz;
-            up[0] = um[0];
-            up[1] = um[1] - T(2) * mn * nx;
-            up[2] = um[2] - T(2) * mn * ny;
-            up[3] = um[3] - T(2) * mn * nz;
-            up[4] = um[4];
-        }
-        T fm[kF3], fp[kF3], lm, lp;
-        normal_flux3(a.g, um, nx, ny, nz, fm, lm);
-        normal_flux3(a.g, up, nx, ny, nz, fp, lp);
-        const T lam = lm > lp ? lm : lp;
-#pragma unroll
-        for (int c = 0; c < kF3; ++c) sJ[e][c][q] = fs * (T(0.5) * (fm[c] - fp[c]) + T(0.5) * lam * (up[c] - um[c]));
-    }
-    __syncthreads();
-    if (!act) return;
-    const T *Dr = a.ops, *Ds = Dr + Np * Np, *Dt = Ds + Np * Np, *LIFT = Dt + Np * Np;
-    T r[kF3] = {};
-#pragma unroll 2
-    for (int j = 0; j < Np; ++j) {
-        const T dr = Dr[j * Np + i], ds = Ds[j * Np + i], dt = Dt[j * Np + i];
-#pragma unroll
-        for (int c = 0; c < kF3; ++c) r[c] -= dr * sC[el][0][c][j] + ds * sC[el][1][c][j] + dt * sC[el][2][c][j];
-    }
-#pragma unroll 2
-    for (int m = 0; m < NF4; ++m) {
-        const T l = LIFT[m * Np + i];
-#pragma unroll
-        for (int c = 0; c < kF3; ++c) r[c] += l * sJ[el][c][m];
-    }
-    const long k = k0 + el;
-    const T dt = a.mode ? T(*a.dt) : T(0);
-#pragma unroll
-    for (int c = 0; c < kF3; ++c) {
-        const long idx = (k * kF3 + c) * Np + i;
-        if (a.mode == 0) {
-            a.rhs[idx] = r[c];
-        } else {
-            const T rr = a.stage == 0 ? dt * r[c] : a.ra * a.R[idx] + dt * r[c];
-            a.R[idx] = rr;
-            a.Uout[idx] = sU[el][c][i] + a.rb * rr;
-        }
-    }
-}
-
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+// Vector types of the matrix-core stage per precision: V4, an accumulator
+// (and a group of four A fragments); V16, one 16-byte access (VW values).
+template <typename T>
+struct VT;
+template <>
+struct VT<float> {
+    typedef f32x4_t V4;
+    typedef f32x4_t V16;
+    static constexpr int VW = 4;
+};
+template <>
+struct VT<double> {
+    typedef f64x4_t V4;
+    typedef f64x2_t V16;
+    static constexpr int VW = 2;
+};
+__device__ __forceinline__ f32x4_t mfma16(float a, float b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4_t mfma16(double a, double b, f64x4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Shape of the matrix-core stage, in four passes over one small B buffer:
 // the face terms (LIFT, 4 Nfp rows), then the contravariant fluxes along
@@ -218,53 +132,63 @@ struct TetM {
     static_assert(15 * Np <= 16 * KPP, "a group's result fits in its B block");
 };
 
+template <typename T>
 struct Stage3MArgs {
     int K, stage, mode;
-    float g, ra, rb;
-    const float *__restrict__ Uin;
-    float *__restrict__ Uout;
-    float *__restrict__ R;
-    float *__restrict__ rhs;
-    const float *__restrict__ geo;
+    T g, ra, rb;
+    const T *__restrict__ Uin;
+    T *__restrict__ Uout;
+    T *__restrict__ R;
+    T *__restrict__ rhs;
+    const T *__restrict__ geo;
     const int *__restrict__ fmap;
     const int *__restrict__ fmask;
-    const f32x4_t *__restrict__ opsA;  // [4][NG][64]: face, then r, s, t fragments (NG = max(NGL, NGD));
-                                       // lane l of fragment z = ks MT + mt: slot z % 4 of group z / 4
+    const typename VT<T>::V4 *__restrict__ opsA;  // [4][NG][64]: face, then r, s, t fragments (NG = max(NGL, NGD));
+                                                  // lane l of fragment z = ks MT + mt: slot z % 4 of group z / 4
     const double *__restrict__ dt;
 };
 
-template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_stage3_mfma(Stage3MArgs a) {
+// The stage body for FP32 (k_stage3_mfma) and FP64 (k_stage3_mfma64).  FP32
+// keeps each node's pointwise fluxes in registers across the three direction
+// passes and requests the Runge-Kutta register before the product; FP64
+// (twice the registers per value) recomputes the fluxes per pass and reads
+// the register in the epilogue.
+template <typename T, int P>
+__device__ __forceinline__ void stage3_mfma_body(const Stage3MArgs<T> &a) {
     using S = TetM<P>;
+    using V4 = typename VT<T>::V4;
+    using V16 = typename VT<T>::V16;
+    constexpr int VW = VT<T>::VW;
+    constexpr bool F32 = sizeof(T) == 4;
     constexpr int Np = S::Np, NF4 = S::NF4, KSD = S::KSD, KSL = S::KSL, KPP = S::KPP, MT = S::MT;
     constexpr int W = S::W, NTH = S::NTH, NT = S::NT, GW = S::GW, EB = S::EB, NGD = S::NGD, NGL = S::NGL;
     constexpr int TPT = S::TPT, PPT = S::PPT;
     constexpr int NG = NGL > NGD ? NGL : NGD;
-    constexpr int NV4 = (EB * kF3 * Np / 4 + NTH - 1) / NTH;
-    static_assert(EB * kF3 * Np % 4 == 0, "a full tile is whole float4");
-    __shared__ __attribute__((aligned(16))) float sB[NT][16][KPP];
-    __shared__ __attribute__((aligned(16))) float sU[EB * kF3 * Np];
-    __shared__ float sG[EB * kGeo3];
+    constexpr int NV = (EB * kF3 * Np / VW + NTH - 1) / NTH;   // 16-byte vectors of a full tile per thread
+    static_assert(EB * kF3 * Np % VW == 0, "a full tile is whole 16-byte vectors");
+    __shared__ __attribute__((aligned(16))) T sB[NT][16][KPP];
+    __shared__ __attribute__((aligned(16))) T sU[EB * kF3 * Np];
+    __shared__ T sG[EB * kGeo3];
     __shared__ int sFM[NF4];
     const long k0 = (long)blockIdx.x * EB;
     const int nel = (int)min((long)EB, (long)a.K - k0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long base = k0 * kF3 * Np;
+    const long base = k0 * kF3 * Np;   // 16-byte aligned: EB is a multiple of 12
     const int nflt = nel * kF3 * Np;
-    const int n4 = nflt / 4;
+    const int nv = nflt / VW;           // whole vectors of this tile (the rest: scalar tail)
     const int ntask = nel * NF4;
 
-    const f32x4_t *U4 = reinterpret_cast<const f32x4_t *>(a.Uin + base);
+    const V16 *Uv = reinterpret_cast<const V16 *>(a.Uin + base);
 #pragma unroll
-    for (int v = 0; v < NV4; ++v) {
+    for (int v = 0; v < NV; ++v) {
         const int z = tid + v * NTH;
-        if (z < n4) reinterpret_cast<f32x4_t *>(sU)[z] = U4[z];
+        if (z < nv) reinterpret_cast<V16 *>(sU)[z] = Uv[z];
     }
-    for (int z = 4 * n4 + tid; z < nflt; z += NTH) sU[z] = a.Uin[base + z];
+    for (int z = VW * nv + tid; z < nflt; z += NTH) sU[z] = a.Uin[base + z];
     for (int z = tid; z < nel * kGeo3; z += NTH) sG[z] = a.geo[k0 * kGeo3 + z];
     for (int z = tid; z < NF4; z += NTH) sFM[z] = a.fmask[z];
     int nbv[TPT];
-    float upn[TPT][kF3];
+    T upn[TPT][kF3];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
         const int task = min(tid + t * NTH, ntask - 1);
@@ -276,14 +200,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     }
     __syncthreads();
 
-    // one pass of the product: B rows [0, 4 ks_count) of every group this
-    // wavefront owns, against A fragments ga (fragment z = ks MT + mt)
-    f32x4_t acc[GW][MT];
+    V4 acc[GW][MT];
 #pragma unroll
     for (int gi = 0; gi < GW; ++gi)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[gi][mt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    auto product = [&](const f32x4_t(&ga)[NG], auto KSC) {
+        for (int mt = 0; mt < MT; ++mt) acc[gi][mt] = V4{T(0), T(0), T(0), T(0)};
+    auto product = [&](const V4(&ga)[NG], auto KSC) {
         constexpr int KSN = decltype(KSC)::value;
 #pragma unroll
         for (int gi = 0; gi < GW; ++gi) {
@@ -291,17 +213,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (3 * t < nel) {
 #pragma unroll
                 for (int ks = 0; ks < KSN; ++ks) {
-                    const float b = sB[t][lane & 15][4 * ks + (lane >> 4)];
+                    const T b = sB[t][lane & 15][4 * ks + (lane >> 4)];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) {
                         const int z = ks * MT + mt;
-                        acc[gi][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[z / 4][z % 4], b, acc[gi][mt], 0, 0, 0);
+                        acc[gi][mt] = mfma16(ga[z / 4][z % 4], b, acc[gi][mt]);
                     }
                 }
             }
         }
     };
-    f32x4_t ga[NG];
+    V4 ga[NG];
 
     // ---- face terms: rows q < 4 Nfp
 #pragma unroll
@@ -310,45 +232,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (task < ntask) {
             const int e = task / NF4, q = task - e * NF4, f = q / (NF4 / 4);
             const int vm = sFM[q];
-            const float *gm = sG + e * kGeo3;
-            const float nx = gm[9 + 3 * f], ny = gm[10 + 3 * f], nz = gm[11 + 3 * f], fs = gm[21 + f];
-            float um[kF3], up[kF3];
+            const T *gm = sG + e * kGeo3;
+            const T nx = gm[9 + 3 * f], ny = gm[10 + 3 * f], nz = gm[11 + 3 * f], fs = gm[21 + f];
+            T um[kF3], up[kF3];
 #pragma unroll
             for (int c = 0; c < kF3; ++c) um[c] = sU[(e * kF3 + c) * Np + vm];
             if (nbv[t] >= 0) {
 #pragma unroll
                 for (int c = 0; c < kF3; ++c) up[c] = upn[t][c];
             } else {
-                const float mn = um[1] * nx + um[2] * ny + um[3] * nz;
+                const T mn = um[1] * nx + um[2] * ny + um[3] * nz;
                 up[0] = um[0];
-                up[1] = um[1] - 2.f * mn * nx;
-                up[2] = um[2] - 2.f * mn * ny;
-                up[3] = um[3] - 2.f * mn * nz;
+                up[1] = um[1] - T(2) * mn * nx;
+                up[2] = um[2] - T(2) * mn * ny;
+                up[3] = um[3] - T(2) * mn * nz;
                 up[4] = um[4];
             }
-            float fm[kF3], fp[kF3], lm, lp;
+            T fm[kF3], fp[kF3], lm, lp;
             normal_flux3(a.g, um, nx, ny, nz, fm, lm);
             normal_flux3(a.g, up, nx, ny, nz, fp, lp);
-            const float lam = lm > lp ? lm : lp;
-            float(*B)[KPP] = sB[e / 3];
+            const T lam = lm > lp ? lm : lp;
+            T(*B)[KPP] = sB[e / 3];
             const int col = (e % 3) * kF3;
 #pragma unroll
-            for (int c = 0; c < kF3; ++c) B[col + c][q] = fs * (0.5f * (fm[c] - fp[c]) + 0.5f * lam * (up[c] - um[c]));
+            for (int c = 0; c < kF3; ++c)
+                B[col + c][q] = fs * (T(0.5) * (fm[c] - fp[c]) + T(0.5) * lam * (up[c] - um[c]));
         }
     }
 #pragma unroll
     for (int g = 0; g < NG; ++g) ga[g] = a.opsA[g * 64 + lane];
-    // the pointwise fluxes of this thread's nodes, kept in registers for the
-    // three direction passes
-    float Fx[PPT][kF3], Fy[PPT][kF3], Fz[PPT][kF3];
+    // FP32: the pointwise fluxes of this thread's nodes, kept in registers
+    // for the three direction passes
+    constexpr int KP_ = F32 ? PPT : 1;
+    T Fx[KP_][kF3], Fy[KP_][kF3], Fz[KP_][kF3];
+    if constexpr (F32) {
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int z = min(tid + p * NTH, nel * Np - 1);
-        const int el = z / Np, i = z - el * Np;
-        float u[kF3];
+        for (int p = 0; p < PPT; ++p) {
+            const int z = min(tid + p * NTH, nel * Np - 1);
+            const int el = z / Np, i = z - el * Np;
+            T u[kF3];
 #pragma unroll
-        for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
-        euler3_flux(a.g, u, Fx[p], Fy[p], Fz[p]);
+            for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
+            euler3_flux(a.g, u, Fx[p], Fy[p], Fz[p]);
+        }
     }
     __syncthreads();
     product(ga, std::integral_constant<int, KSL>());
@@ -361,7 +287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             constexpr int PADR = 4 * KSD - Np, PADN = 16 * PADR;
             for (int z = tid; z < NT * PADN; z += NTH) {
                 const int t = z / PADN, rem = z - t * PADN;
-                sB[t][rem / PADR][Np + rem % PADR] = 0.f;
+                sB[t][rem / PADR][Np + rem % PADR] = T(0);
             }
         }
 #pragma unroll
@@ -369,12 +295,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             const int z = tid + p * NTH;
             if (z < nel * Np) {
                 const int el = z / Np, i = z - el * Np;
-                const float *m = sG + el * kGeo3 + 3 * d;
-                const float m0 = m[0], m1 = m[1], m2 = m[2];
-                float(*B)[KPP] = sB[el / 3];
+                const T *m = sG + el * kGeo3 + 3 * d;
+                const T m0 = m[0], m1 = m[1], m2 = m[2];
+                T(*B)[KPP] = sB[el / 3];
                 const int col = (el % 3) * kF3;
+                if constexpr (F32) {
 #pragma unroll
-                for (int c = 0; c < kF3; ++c) B[col + c][i] = m0 * Fx[p][c] + m1 * Fy[p][c] + m2 * Fz[p][c];
+                    for (int c = 0; c < kF3; ++c) B[col + c][i] = m0 * Fx[p][c] + m1 * Fy[p][c] + m2 * Fz[p][c];
+                } else {
+                    T u[kF3], F[kF3], G[kF3], H[kF3];
+#pragma unroll
+                    for (int c = 0; c < kF3; ++c) u[c] = sU[(el * kF3 + c) * Np + i];
+                    euler3_flux(a.g, u, F, G, H);
+#pragma unroll
+                    for (int c = 0; c < kF3; ++c) B[col + c][i] = m0 * F[c] + m1 * G[c] + m2 * H[c];
+                }
             }
         }
 #pragma unroll
@@ -382,12 +317,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         __syncthreads();
         product(ga, std::integral_constant<int, KSD>());
     }
-    f32x4_t r4[NV4];
+    constexpr int NR = F32 ? NV : 1;
+    V16 rv[NR];
     const bool rk_read = a.mode && a.stage > 0;
+    if constexpr (F32) {
 #pragma unroll
-    for (int v = 0; v < NV4; ++v) {
-        const int z = min(tid + v * NTH, n4 - 1);
-        r4[v] = rk_read && n4 > 0 ? reinterpret_cast<const f32x4_t *>(a.R + base)[z] : f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int v = 0; v < NV; ++v) {
+            const int z = min(tid + v * NTH, nv - 1);
+            rv[v] = rk_read && nv > 0 ? reinterpret_cast<const V16 *>(a.R + base)[z] : V16{};
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -395,49 +333,69 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const int t = wave + gi * W;
         const int col = lane & 15, le = col / kF3, c = col - le * kF3;
         if (col < 15 && 3 * t + le < nel) {
-            float *res = &sB[t][0][0];
+            T *res = &sB[t][0][0];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int i = 16 * mt + 4 * (lane >> 4) + r;
+                    // output row of accumulator slot r: four consecutive rows
+                    // per 16-lane group in FP32, rows interleaved by 4 in FP64
+                    const int i = F32 ? 16 * mt + 4 * (lane >> 4) + r : 16 * mt + (lane >> 4) + 4 * r;
                     if (i < Np) res[(le * kF3 + c) * Np + i] = acc[gi][mt][r];
                 }
         }
     }
     __syncthreads();
 
-    const float dt = a.mode ? float(*a.dt) : 0.f;
-    auto result = [&](int z) -> float {
+    // ---- epilogue: Runge-Kutta update (or the bare rhs) in 16-byte vectors
+    // where the tile is whole vectors
+    const T dt = a.mode ? T(*a.dt) : T(0);
+    auto result = [&](int z) -> T {
         const int el = z / (kF3 * Np), off = z - el * (kF3 * Np);
         return (&sB[el / 3][0][0])[(el % 3) * kF3 * Np + off];
     };
 #pragma unroll
-    for (int v = 0; v < NV4; ++v) {
-        const int z4 = tid + v * NTH;
-        if (z4 < n4) {
-            const int z = 4 * z4;
-            const f32x4_t rh = {result(z), result(z + 1), result(z + 2), result(z + 3)};
+    for (int v = 0; v < NV; ++v) {
+        const int zv = tid + v * NTH;
+        if (zv < nv) {
+            V16 rh;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) rh[e] = result(VW * zv + e);
             if (a.mode == 0) {
-                reinterpret_cast<f32x4_t *>(a.rhs + base)[z4] = rh;
+                reinterpret_cast<V16 *>(a.rhs + base)[zv] = rh;
             } else {
-                const f32x4_t rr = a.stage == 0 ? dt * rh : a.ra * r4[v] + dt * rh;
-                reinterpret_cast<f32x4_t *>(a.R + base)[z4] = rr;
-                reinterpret_cast<f32x4_t *>(a.Uout + base)[z4] = reinterpret_cast<const f32x4_t *>(sU)[z4] + a.rb * rr;
+                V16 rold;
+                if constexpr (F32)
+                    rold = rv[v];
+                else
+                    rold = rk_read ? reinterpret_cast<const V16 *>(a.R + base)[zv] : V16{};
+                const V16 rr = a.stage == 0 ? dt * rh : a.ra * rold + dt * rh;
+                reinterpret_cast<V16 *>(a.R + base)[zv] = rr;
+                reinterpret_cast<V16 *>(a.Uout + base)[zv] = reinterpret_cast<const V16 *>(sU)[zv] + a.rb * rr;
             }
         }
     }
-    for (int z = 4 * n4 + tid; z < nflt; z += NTH) {
-        const float rh = result(z);
+    for (int z = VW * nv + tid; z < nflt; z += NTH) {
+        const T rh = result(z);
         const long idx = base + z;
         if (a.mode == 0) {
             a.rhs[idx] = rh;
         } else {
-            const float rr = a.stage == 0 ? dt * rh : a.ra * a.R[idx] + dt * rh;
+            const T rr = a.stage == 0 ? dt * rh : a.ra * a.R[idx] + dt * rh;
             a.R[idx] = rr;
             a.Uout[idx] = sU[z] + a.rb * rr;
         }
     }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_stage3_mfma(Stage3MArgs<float> a) {
+    stage3_mfma_body<float, P>(a);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_stage3_mfma64(Stage3MArgs<double> a) {
+    stage3_mfma_body<double, P>(a);
 }
 
 // Time-step bound in FP64 at every face node: (P+1)^2 Fscale (|v| + c) / 2,
@@ -449,8 +407,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(kB3) void k_cfl3(int K, double g, const T *__restrict__ U, const T *__restrict__ geo,
                                              const int *__restrict__ fmask, unsigned long long *vmax,
                                              int *flag) {
-    using S = Tet<T, P>;
-    constexpr int Np = S::Np, NF4 = S::NF4, EB = S::EB;
+    constexpr int Np = (P + 1) * (P + 2) * (P + 3) / 6, NF4 = Bound3<P>::NF4, EB = Bound3<P>::EB;
     __shared__ double sRed[kB3 / 64];
     const long k0 = (long)blockIdx.x * EB;
     const int nel = (int)min((long)EB, (long)K - k0);
@@ -571,10 +528,9 @@ auto with_order3(int P, F &&f) {
 
 }  // namespace
 
-int tet3_blocks(int K, int P, bool fp32) {
+int tet3_blocks(int K, int P) {
     return with_order3(P, [&](auto PC) {
-        constexpr int P_ = decltype(PC)::value;
-        const int EB = fp32 ? Tet<float, P_>::EB : Tet<double, P_>::EB;
+        constexpr int EB = Bound3<decltype(PC)::value>::EB;
         return (K + EB - 1) / EB;
     });
 }
@@ -595,17 +551,17 @@ constexpr int tet3_ng() {
     return S::NGL > S::NGD ? S::NGL : S::NGD;
 }
 
-size_t tet3_mfma_opsA_floats(int P) {
+size_t tet3_mfma_opsA_values(int P) {
     return with_order3(P, [](auto PC) { return size_t(4) * tet3_ng<decltype(PC)::value>() * 64 * 4; });
 }
 
-void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
-                         float *out) {
+template <typename T>
+static void fill_opsA3(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT, T *out) {
     with_order3(P, [&](auto PC) {
         constexpr int PP = decltype(PC)::value;
         using S = TetM<PP>;
         constexpr int Np = S::Np, NF4 = S::NF4, MT = S::MT, NG = tet3_ng<PP>();
-        std::fill(out, out + size_t(4) * NG * 64 * 4, 0.f);
+        std::fill(out, out + size_t(4) * NG * 64 * 4, T(0));
         const double *D[3] = {Dr, Ds, Dt};
         for (int pass = 0; pass < 4; ++pass) {
             const int ksn = pass == 0 ? S::KSL : S::KSD;
@@ -621,44 +577,27 @@ void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double
                                 v = -D[pass - 1][m * Np + k];
                         }
                         const int z = ks * MT + mt;
-                        out[((size_t(pass) * NG + z / 4) * 64 + l) * 4 + z % 4] = float(v);
+                        out[((size_t(pass) * NG + z / 4) * 64 + l) * 4 + z % 4] = T(v);
                     }
         }
         return 0;
     });
 }
 
-static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                              hipStream_t st) {
-    Stage3MArgs a;
-    a.K = m.K;
-    a.stage = stage;
-    a.mode = rhs ? 0 : 1;
-    a.g = float(m.gamma);
-    a.ra = float(rk_a(stage));
-    a.rb = float(rk_b(stage));
-    a.Uin = static_cast<const float *>(Uin);
-    a.Uout = static_cast<float *>(Uout);
-    a.R = static_cast<float *>(R);
-    a.rhs = static_cast<float *>(rhs);
-    a.geo = m.geo32;
-    a.fmap = m.fmap;
-    a.fmask = m.fmask;
-    a.opsA = reinterpret_cast<const f32x4_t *>(m.opsA);
-    a.dt = m.scal + S_DT;
-    return with_order3(m.P, [&](auto PC) {
-        constexpr int P = decltype(PC)::value;
-        using S = TetM<P>;
-        const int blocks = (m.K + S::EB - 1) / S::EB;
-        hipLaunchKernelGGL((k_stage3_mfma<P>), dim3(blocks), dim3(S::NTH), 0, st, a);
-        return hipGetLastError();
-    });
+void tet3_mfma_fill_opsA(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                         float *out) {
+    fill_opsA3<float>(P, Dr, Ds, Dt, LIFT, out);
+}
+
+void tet3_mfma_fill_opsA64(int P, const double *Dr, const double *Ds, const double *Dt, const double *LIFT,
+                           double *out) {
+    fill_opsA3<double>(P, Dr, Ds, Dt, LIFT, out);
 }
 
 template <typename T>
-static hipError_t stage3_t(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                           hipStream_t st) {
-    Stage3Args<T> a;
+static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                              hipStream_t st) {
+    Stage3MArgs<T> a;
     a.K = m.K;
     a.stage = stage;
     a.mode = rhs ? 0 : 1;
@@ -672,26 +611,31 @@ static hipError_t stage3_t(const Tet3Mesh &m, const void *Uin, void *Uout, void 
     a.geo = static_cast<const T *>(m.fp32 ? static_cast<const void *>(m.geo32) : m.geo64);
     a.fmap = m.fmap;
     a.fmask = m.fmask;
-    a.ops = static_cast<const T *>(m.fp32 ? static_cast<const void *>(m.ops32) : m.ops64);
+    a.opsA = reinterpret_cast<const typename VT<T>::V4 *>(m.fp32 ? static_cast<const void *>(m.opsA)
+                                                                  : static_cast<const void *>(m.opsA64));
     a.dt = m.scal + S_DT;
     return with_order3(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        hipLaunchKernelGGL((k_stage3<T, P>), dim3(tet3_blocks(m.K, P, m.fp32)), dim3(kB3), 0, st, a);
+        using S = TetM<P>;
+        const int blocks = (m.K + S::EB - 1) / S::EB;
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_stage3_mfma<P>), dim3(blocks), dim3(S::NTH), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_stage3_mfma64<P>), dim3(blocks), dim3(S::NTH), 0, st, a);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                          hipStream_t st) {
-    if (m.fp32 && m.opsA) return stage3_mfma(m, Uin, Uout, R, rhs, stage, st);
-    return m.fp32 ? stage3_t<float>(m, Uin, Uout, R, rhs, stage, st)
-                  : stage3_t<double>(m, Uin, Uout, R, rhs, stage, st);
+    return m.fp32 ? stage3_mfma<float>(m, Uin, Uout, R, rhs, stage, st)
+                  : stage3_mfma<double>(m, Uin, Uout, R, rhs, stage, st);
 }
 
 hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStream_t st) {
     hipError_t e = with_order3(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
-        const dim3 grid(tet3_blocks(m.K, P, m.fp32)), block(kB3);
+        const dim3 grid(tet3_blocks(m.K, P)), block(kB3);
         if (m.fp32)
             hipLaunchKernelGGL((k_cfl3<float, P>), grid, block, 0, st, m.K, m.gamma, static_cast<const float *>(U),
                                m.geo32, m.fmask, m.vmax, m.flag);
