@@ -210,20 +210,55 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<T> a) {
     const T rx = a.geo[(k * 4 + 0) * Np + i], sx = a.geo[(k * 4 + 1) * Np + i];
     const T ry = a.geo[(k * 4 + 2) * Np + i], sy = a.geo[(k * 4 + 3) * Np + i];
     const T dt = a.mode ? T(*a.dt) : T(0);
+    // at P = 5 the contractions run node by node across the four fields, so
+    // that each operator entry is read from LDS once for all of them (the
+    // same sums in the same order as field by field)
+    T vol[kRowsInRegs ? 1 : kFields], lift[kRowsInRegs ? 1 : kFields];
+    if constexpr (!kRowsInRegs) {
+        T drf[kFields] = {}, dsf[kFields] = {}, drg[kFields] = {}, dsg[kFields] = {};
+#pragma unroll 3
+        for (int j = 0; j < Np; ++j) {
+            const T dj = dr(j), sj = ds(j);
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) {
+                const T fv = sF[el][c][j], gv = sF[el][kFields + c][j];
+                drf[c] += dj * fv;
+                dsf[c] += sj * fv;
+                drg[c] += dj * gv;
+                dsg[c] += sj * gv;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kFields; ++c) {
+            vol[c] = -(rx * drf[c] + sx * dsf[c] + ry * drg[c] + sy * dsg[c]);
+            lift[c] = vol[c];
+        }
+#pragma unroll 3
+        for (int q = 0; q < NF3; ++q) {
+            const T l = lf(q);
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) lift[c] += l * sJ[el][c][q];
+        }
+    }
 #pragma unroll
     for (int c = 0; c < kFields; ++c) {
-        T drf = 0, dsf = 0, drg = 0, dsg = 0;
+        T val;
+        if constexpr (!kRowsInRegs) {
+            val = lift[c];
+        } else {
+            T drf = 0, dsf = 0, drg = 0, dsg = 0;
 #pragma unroll
-        for (int j = 0; j < Np; ++j) {
-            const T fv = sF[el][c][j], gv = sF[el][kFields + c][j];
-            drf += dr(j) * fv;
-            dsf += ds(j) * fv;
-            drg += dr(j) * gv;
-            dsg += ds(j) * gv;
+            for (int j = 0; j < Np; ++j) {
+                const T fv = sF[el][c][j], gv = sF[el][kFields + c][j];
+                drf += dr(j) * fv;
+                dsf += ds(j) * fv;
+                drg += dr(j) * gv;
+                dsg += ds(j) * gv;
+            }
+            val = -(rx * drf + sx * dsf + ry * drg + sy * dsg);
+#pragma unroll
+            for (int q = 0; q < NF3; ++q) val += lf(q) * sJ[el][c][q];
         }
-        T val = -(rx * drf + sx * dsf + ry * drg + sy * dsg);
-#pragma unroll
-        for (int q = 0; q < NF3; ++q) val += lf(q) * sJ[el][c][q];
         const long idx = (k * kFields + c) * Np + i;
         if (a.mode == 0) {
             a.rhs[idx] = val;
@@ -790,6 +825,9 @@ __global__ __launch_bounds__(kBlock) void k_cfl_finish(int n, const double *__re
                                                        double *__restrict__ scal) {
     __shared__ double sh[kBlock];
     double v = 0.0;
+    // unrolled so that eight loads are in flight per wait (the maximum is
+    // exact in any order)
+#pragma unroll 8
     for (int b = threadIdx.x; b < n; b += kBlock) v = v > partial[b] ? v : partial[b];
     const double vmax = block_reduce(v, sh, MaxOp());
     if (threadIdx.x == 0) {
@@ -806,6 +844,7 @@ __global__ __launch_bounds__(kBlock) void k_cfl_finish_vmax(int n, const double 
                                                             unsigned long long *__restrict__ slot) {
     __shared__ double sh[kBlock];
     double v = 0.0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < n; b += kBlock) v = v > partial[b] ? v : partial[b];
     const double vmax = block_reduce(v, sh, MaxOp());
     // the bound in the first slot, zeros in the others
