@@ -60,10 +60,12 @@ enum dg_status {
     DG_EBUSY = -6        /* batch admission: no free slot, or over the HBM budget */
 };
 
-/* There is no separate DG_FP64 = 1 (FP64 state on the FP64 matrix cores):
- * FP64 handles use DG_FP64_PLAIN, whose contractions run on the VALUs. */
+/* There is no separate DG_FP64 = 1: FP64 handles use DG_FP64_PLAIN, FP64
+ * throughout.  Its stage runs on the VALUs, except for meshes whose elements
+ * are all straight and carry no artificial viscosity, where the stage's
+ * product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64). */
 enum dg_precision {
-    DG_FP64_PLAIN = 0,   /* FP64 throughout; straightforward VALU kernels */
+    DG_FP64_PLAIN = 0,   /* FP64 throughout */
     DG_FP32 = 2,         /* FP32 state and fused stage kernel; FP64 setup,
                             time step and reductions */
     DG_FP32_BF16X3 = 3   /* as DG_FP32, but the stage's matrix product runs as

@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdg.so")
-SOURCES = ["kernels.hip", "stage_mfma.hip", "weak.hip", "tet3d.hip", "api.cpp", "api3.cpp", "refelem.cpp"]
+SOURCES = ["kernels.hip", "stage_mfma.hip", "stage64.hip", "weak.hip", "tet3d.hip", "api.cpp", "api3.cpp",
+           "refelem.cpp"]
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay disabled; hipcc's host pass warns that it

@@ -3,6 +3,8 @@
 // preceded by the sensor and the viscous-gradient kernels).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -380,6 +382,28 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
         fail(DG_EGEOM, std::to_string(counts[1]) +
                            " interior face nodes whose normal is not minus the neighbour's");
         return cleanup(DG_EGEOM);
+    }
+    if (!dm.fp32 && !dm.weak && !dm.av) {
+        // an FP64 handle whose elements are all straight runs the stage's
+        // product on the FP64 matrix cores (k_stage_mfma64)
+        int *flags_d;
+        if ((rc = m->alloc(&flags_d, size_t(K)))) return cleanup(rc);
+        SETUP_TRY(launch_affine_flags(dm, flags_d, st));
+        std::vector<int> flags(K);
+        SETUP_TRY(hipMemcpyAsync(flags.data(), flags_d, sizeof(int) * K, hipMemcpyDeviceToHost, st));
+        SETUP_TRY(hipStreamSynchronize(st));
+        if (std::all_of(flags.begin(), flags.end(), [](int f) { return f != 0; })) {
+            const size_t nA = mfma64_opsA_values(P);
+            double *opsA64_d, *geoA64_d;
+            if ((rc = m->alloc(&opsA64_d, nA)) || (rc = m->alloc(&geoA64_d, size_t(K) * 16))) return cleanup(rc);
+            SETUP_TRY(launch_pack_affine64(dm, geoA64_d, st));
+            std::vector<double> opsA64(nA);
+            mfma64_fill_opsA(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsA64.data());
+            SETUP_TRY(hipMemcpyAsync(opsA64_d, opsA64.data(), sizeof(double) * nA, hipMemcpyHostToDevice, st));
+            SETUP_TRY(hipStreamSynchronize(st));
+            dm.opsA64 = opsA64_d;
+            dm.geoA64 = geoA64_d;
+        }
     }
     if (dm.fp32) {
         float *geo32, *fgeo32, *emax32, *ops32;

@@ -1076,9 +1076,11 @@ hipError_t launch_cast(const double *src, float *dst, size_t n, hipStream_t st) 
 hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                         const void *eps, const void *Q, hipStream_t st) {
     // the weak form: its own kernel; FP32 (with or without viscosity): the
-    // matrix-core kernel; FP64: VALU
+    // matrix-core kernel; FP64: the FP64 matrix cores for a mesh of straight
+    // elements without viscosity, else VALU
     if (m.weak) return launch_stage_weak(m, Uin, Uout, R, rhs, stage, st);
     if (m.fp32) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st, eps, Q);
+    if (m.opsA64 && !m.av) return launch_stage_mfma64(m, Uin, Uout, R, rhs, stage, st);
     return stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }
 

@@ -60,6 +60,9 @@ struct DevMesh {
     const int *cpre = nullptr;      // [K + 1] number of curved elements before element k
     const float *geoC = nullptr;    // [Kc][4 Np + 9 Nfp] curved geometry
     const float *opsA = nullptr;    // MFMA A operand table
+    const double *opsA64 = nullptr; // FP64 handles of straight elements without viscosity: the
+                                    // FP64 matrix-core stage's A operand (null: the VALU stage)
+    const double *geoA64 = nullptr; // ... and its [K][16] geometry records (k_pack_affine64)
     const unsigned *opsB = nullptr; // BF16x3 A operand table (hi and lo splits)
     int Kc = 0;
     int ncu = 256;                  // compute units of the device
@@ -72,6 +75,14 @@ struct DevMesh {
     double *partial = nullptr;
     int npartial = 0;
 };
+
+// FP64 stage on the matrix cores (stage64.hip): A operand [LIFT -Dr -Ds] in
+// lane order, and the launch
+size_t mfma64_opsA_values(int P);
+void mfma64_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, double *out);
+hipError_t launch_stage_mfma64(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                               hipStream_t st);
+hipError_t launch_pack_affine64(const DevMesh &m, double *rec, hipStream_t st);
 
 // offsets of the operators in the ops tables
 inline size_t ops_size(int Np, int Nfp) { return size_t(Np) * Np * 3 + size_t(Np) * 3 * Nfp; }
