@@ -67,8 +67,11 @@ struct Stage64Args {
     const double *__restrict__ dt;
 };
 
+// five waves per SIMD (at most 96 registers): 901 us on the 1M-element
+// P = 5 mesh, against 1,003 us at the four the default register budget gives
+// and 1,151 us at six (which spills)
 template <int P>
-__global__ __launch_bounds__(256) void k_stage_mfma64(Stage64Args a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_stage_mfma64(Stage64Args a) {
     using S = Tri64<P>;
     constexpr int Np = S::Np, Nfp = S::Nfp, NF3 = S::NF3, KSD = S::KSD, KSL = S::KSL, KPP = S::KPP;
     constexpr int MT = S::MT, NG = S::NG, W = S::W, NTH = S::NTH, NT = S::NT, EB = S::EB;
