@@ -211,3 +211,27 @@ def test_periodic_run_conserves(precision):
     drift = np.abs(t1 - t0) / scale
     print(f"relative drift {drift}")
     assert drift.max() < (1e-13 if precision == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_element_with_four_walls(precision):
+    """One tetrahedron whose four faces are walls (the smallest ragged tile:
+    one element of a 12-element block) at P = 1..4."""
+    from paper_1208_4772_amd import dg3
+    from meshgen.tets import TetGrid, connect3
+    X = np.array([[[0.1, 0.0, 0.05], [1.0, 0.1, 0.0], [0.05, 0.9, 0.1], [0.0, 0.1, 1.1]]])
+    EToV = np.array([[0, 1, 2, 3]])
+    g = TetGrid(EToV, X, None)
+    g.EToE, g.EToF, g.bc = connect3(EToV)
+    assert (g.bc == 1).all()
+    for P in (1, 2, 3, 4):
+        print(f"[tet3d one element P={P} {precision}]", flush=True)
+        o = T.Oracle3D(T.TetMesh(EToV, X, None), P)
+        s = dg3.Solver3D.from_mesh(g, P, precision=precision)
+        r, st, t = dg3.reference_nodes3(P)
+        U0 = smooth_state3(affine_node_coordinates(g, r, st, t), seed=P)
+        ref = o.rhs(U0)
+        e = rel_l2(host(s.rhs(s.state(U0))), ref)
+        print(f"rel L2 {e:.3e}")
+        assert e < TOL[precision]
+        s.close()
