@@ -31,7 +31,8 @@ extern "C" {
 typedef struct {
     int K;                        /* elements, >= 1 */
     int P;                        /* order, 1..4 */
-    int precision;                /* DG_FP64_PLAIN or DG_FP32 */
+    int precision;                /* DG_FP64_PLAIN or DG_FP32 (both run the stage on the
+                                     matrix cores, in FP64 and FP32 respectively) */
     const int *EToV;              /* [K][4] global vertex ids: faces match by their vertex triples */
     const int *EToE;              /* [K][4] neighbour across face f (the element itself at a wall) */
     const int *EToF;              /* [K][4] the neighbour's face */
