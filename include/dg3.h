@@ -93,7 +93,9 @@ int dg3_buffer_bytes(const dg3_mesh *mesh, size_t *state_bytes, size_t *work_byt
  * aligned), DG_EDEVICE. */
 int dg3_rhs(dg3_mesh *mesh, const void *U, void *rhs, void *stream);
 
-/* nsteps LSERK steps of U in place.  dt_fixed > 0: that step; otherwise
+/* nsteps LSERK steps of U in place, pairs of steps replayed from a graph
+ * captured on the handle's own stream (built on the first call with these
+ * U, work and dt_fixed, kept until they change).  dt_fixed > 0: that step; otherwise
  * dt = CFL / max over face nodes of (P+1)^2 Fscale (|v| + c) / 2, in FP64
  * from the state at the start of each step.  *stats (may be NULL) receives
  * steps, status, t, dt_min, dt_max and the device time (totals and

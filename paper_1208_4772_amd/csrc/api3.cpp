@@ -352,11 +352,63 @@ struct dg3_mesh {
     // offset of each buffer in the work area: the stage kernels move whole
     // tiles as 16-byte vectors, so every buffer starts 256-byte aligned
     size_t slot_bytes() const { return (state_bytes() + 255) / 256 * 256; }
+    // two steps captured into a graph on a private stream and replayed on
+    // the caller's; rebuilt when the buffers or the fixed step change (the
+    // kernels read dt and the bound from device memory)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    const void *graph_U = nullptr, *graph_work = nullptr;
+    double graph_dt = 0.0;
     ~dg3_mesh() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (done) (void)hipEventDestroy(done);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
+
+namespace {
+
+// One LSERK step: the bound and dt, then the five stages U -> A -> B -> A
+// -> B -> U with the register R.
+hipError_t enqueue_step3(const dg3_mesh *h, void *U, void *work, double dt_fixed, hipStream_t st) {
+    const Tet3Mesh &m = h->m;
+    char *w = static_cast<char *>(work);
+    const size_t sb = h->slot_bytes();
+    void *R = w, *A = w + sb, *B = w + 2 * sb;
+    void *in[5] = {U, A, B, A, B};
+    void *outp[5] = {A, B, A, B, U};
+    hipError_t e = launch_cfl3(m, U, dt_fixed, st);
+    for (int s = 0; s < 5 && e == hipSuccess; ++s) e = launch_stage3(m, in[s], outp[s], R, nullptr, s, st);
+    return e;
+}
+
+int ensure_graph3(dg3_mesh *h, void *U, void *work, double dt_fixed) {
+    if (h->graph && h->graph_U == U && h->graph_work == work && h->graph_dt == dt_fixed) return DG_OK;
+    if (h->graph) {
+        HIP3(hipGraphExecDestroy(h->graph));
+        h->graph = nullptr;
+    }
+    if (!h->cap_stream) HIP3(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP3(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = enqueue_step3(h, U, work, dt_fixed, h->cap_stream);
+    if (e == hipSuccess) e = enqueue_step3(h, U, work, dt_fixed, h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+    if (e != hipSuccess || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return report_error(DG_EDEVICE, std::string("step capture: ") + hipGetErrorString(e != hipSuccess ? e : ec));
+    }
+    const hipError_t ei = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return report_error(DG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    h->graph_U = U;
+    h->graph_work = work;
+    h->graph_dt = dt_fixed;
+    return DG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -509,20 +561,17 @@ int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_ru
     if (misaligned(U) || misaligned(work)) return report_error(DG_EINVAL, "U and work must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Tet3Mesh &m = h->m;
-    char *w = static_cast<char *>(work);
-    const size_t sb = h->slot_bytes();
-    void *R = w, *A = w + sb, *B = w + 2 * sb;
-    void *in[5] = {U, A, B, A, B};
-    void *outp[5] = {A, B, A, B, U};
+    if (nsteps >= 2)
+        if (int rc = ensure_graph3(h, U, work, dt_fixed)) return rc;
     hipEvent_t e0, e1;
     HIP3(hipEventCreate(&e0));
     HIP3(hipEventCreate(&e1));
     HIP3(launch_reset3(m, st));
     HIP3(hipEventRecord(e0, st));
-    for (int n = 0; n < nsteps; ++n) {
-        HIP3(launch_cfl3(m, U, dt_fixed, st));
-        for (int s = 0; s < 5; ++s) HIP3(launch_stage3(m, in[s], outp[s], R, nullptr, s, st));
-    }
+    int n = 0;
+    if (nsteps >= 2)
+        for (; n + 2 <= nsteps; n += 2) HIP3(hipGraphLaunch(h->graph, st));
+    for (; n < nsteps; ++n) HIP3(enqueue_step3(h, U, work, dt_fixed, st));
     HIP3(hipEventRecord(e1, st));
     double scal[S_NSCAL];
     int flag = 0;

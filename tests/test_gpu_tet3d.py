@@ -235,3 +235,21 @@ def test_single_element_with_four_walls(precision):
         print(f"rel L2 {e:.3e}")
         assert e < TOL[precision]
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replays_equal_eager_steps(precision):
+    """Runs of 2 and 4 steps replay a captured two-step graph; runs of one
+    step launch eagerly: after the same number of steps the states agree
+    bitwise, replay after replay, with eager work and synchronisation in
+    between."""
+    print(f"[tet3d graph vs eager {precision}]", flush=True)
+    g, o, s, xyz = setup(3, 3, precision, periodic=False, jitter=0.1, seed=13)
+    U0 = smooth_state3(xyz, seed=21)
+    Ug, Ue = s.state(U0), s.state(U0)
+    for rep in range(3):
+        s.run(Ug, 4 if rep != 1 else 2)
+        for _ in range(4 if rep != 1 else 2):
+            s.run(Ue, 1)
+        s.rhs(Ue)
+        assert np.array_equal(host(Ug), host(Ue)), rep
