@@ -271,3 +271,31 @@ def test_lift_matches_exact_rational_arithmetic(P):
     """LIFT against its definition evaluated in exact rational arithmetic
     (a different basis and no rounding): agreement to FP64 rounding."""
     np.testing.assert_allclose(T.ref(P).LIFT, _exact_lift(P), rtol=0, atol=5e-14 * (P + 1) ** 2)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_time_step_by_hand_on_one_tetrahedron(P):
+    """The corner tetrahedron (0,0,0), (1,0,0), (0,1,0), (0,0,1): J = (1/6) /
+    (4/3) = 1/8; the three right-angled faces have area 1/2 (Fscale = 2), the
+    slanted one sqrt(3)/2 (Fscale = 2 sqrt 3).  A uniform state rho = 1.2,
+    v = (0.3, 0.4, 0), p = 1 has |v| + c = 0.5 + sqrt(1.4 / 1.2), so
+    dt = CFL / (1/2 (P+1)^2 2 sqrt3 (0.5 + sqrt(1.4/1.2)))."""
+    X = np.array([[[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]])
+    m = T.TetMesh(np.array([[0, 1, 2, 3]]), X, None)
+    o = T.Oracle3D(m, P, cfl=0.7)
+    assert abs(o.geo.J[0] - 1.0 / 8.0) < 1e-15
+    np.testing.assert_allclose(np.sort(o.geo.Fscale[0]), [2.0, 2.0, 2.0, 2.0 * math.sqrt(3.0)], rtol=1e-14)
+    one = np.ones((1, o.R.Np))
+    U = T.primitive_to_conserved(1.2 * one, 0.3 * one, 0.4 * one, 0 * one, one)
+    lam = 0.5 + math.sqrt(1.4 / 1.2)
+    expect = 0.7 / (0.5 * (P + 1) ** 2 * 2.0 * math.sqrt(3.0) * lam)
+    assert abs(o.dt(U) - expect) < 1e-14 * expect
+    # the fastest node on a slower face does not set the step: speed up one
+    # node that lies on the right-angled faces only (the corner at the origin)
+    corner = int(np.argmin(o.R.r + o.R.s + o.R.t))        # (-1, -1, -1)
+    U2 = U.copy()
+    U2[0, 1, corner] = 1.2 * 0.9                          # u = 0.9 there
+    U2[0, 4, corner] = 1.0 / 0.4 + 0.5 * 1.2 * (0.9 ** 2 + 0.4 ** 2)
+    lam2 = math.sqrt(0.9 ** 2 + 0.4 ** 2) + math.sqrt(1.4 / 1.2)
+    expect2 = 0.7 / (0.5 * (P + 1) ** 2 * max(2.0 * lam2, 2.0 * math.sqrt(3.0) * lam))
+    assert abs(o.dt(U2) - expect2) < 1e-14 * expect2
