@@ -87,3 +87,11 @@ def test_stage_times_and_quadrature_order():
 def test_first_stage_ignores_register():
     assert A[0] == 0
     assert np.isclose(float(sum(B)), float(sum(B)))
+
+
+def test_3d_oracle_uses_the_pinned_coefficients():
+    """The 3D oracle's own copy of the coefficients rounds the rationals
+    pinned above."""
+    from oracle import tet3d
+    assert tet3d.RK_A == tuple(float(a) for a in A)
+    assert tet3d.RK_B == tuple(float(b) for b in B)
