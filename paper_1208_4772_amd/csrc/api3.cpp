@@ -369,8 +369,9 @@ struct dg3_mesh {
 
 namespace {
 
-// One LSERK step: the bound and dt, then the five stages U -> A -> B -> A
-// -> B -> U with the register R.
+// One LSERK step: dt from the bound in the slots, then the five stages
+// U -> A -> B -> A -> B -> U with the register R, the last of which leaves
+// the next step's bound in the slots (a run's first bound: launch_bound3).
 hipError_t enqueue_step3(const dg3_mesh *h, void *U, void *work, double dt_fixed, hipStream_t st) {
     const Tet3Mesh &m = h->m;
     char *w = static_cast<char *>(work);
@@ -378,8 +379,8 @@ hipError_t enqueue_step3(const dg3_mesh *h, void *U, void *work, double dt_fixed
     void *R = w, *A = w + sb, *B = w + 2 * sb;
     void *in[5] = {U, A, B, A, B};
     void *outp[5] = {A, B, A, B, U};
-    hipError_t e = launch_cfl3(m, U, dt_fixed, st);
-    for (int s = 0; s < 5 && e == hipSuccess; ++s) e = launch_stage3(m, in[s], outp[s], R, nullptr, s, st);
+    hipError_t e = launch_dt3(m, dt_fixed, st);
+    for (int s = 0; s < 5 && e == hipSuccess; ++s) e = launch_stage3(m, in[s], outp[s], R, nullptr, s, s == 4, st);
     return e;
 }
 
@@ -550,7 +551,7 @@ int dg3_rhs(dg3_mesh *h, const void *U, void *rhs, void *stream) {
     if (U == rhs) return report_error(DG_EINVAL, "U and rhs must not alias");
     if (misaligned(U) || misaligned(rhs)) return report_error(DG_EINVAL, "states must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    HIP3(launch_stage3(h->m, U, nullptr, nullptr, rhs, 0, st));
+    HIP3(launch_stage3(h->m, U, nullptr, nullptr, rhs, 0, false, st));
     (void)hipEventRecord(h->done, st);
     return DG_OK;
 }
@@ -568,6 +569,7 @@ int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_ru
     HIP3(hipEventCreate(&e1));
     HIP3(launch_reset3(m, st));
     HIP3(hipEventRecord(e0, st));
+    if (nsteps > 0) HIP3(launch_bound3(m, U, st));
     int n = 0;
     if (nsteps >= 2)
         for (; n + 2 <= nsteps; n += 2) HIP3(hipGraphLaunch(h->graph, st));

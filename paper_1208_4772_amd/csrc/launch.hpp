@@ -226,11 +226,14 @@ void tet3_mfma_fill_opsA64(int P, const double *Dr, const double *Ds, const doub
 hipError_t launch_geometry3(int K, const double *X, double *geo, int *count, hipStream_t st);
 // zeroes the scalars (dt_min = +inf), the bound and the flag
 hipError_t launch_reset3(const Tet3Mesh &m, hipStream_t st);
+// one stage (rhs != null: the bare rhs); bound: also the time-step bound of
+// the new state into the slots and its state check (a step's last stage)
 hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                         hipStream_t st);
-// time-step bound (FP64, from the state) and dt = CFL / bound (dt_fixed > 0
-// overrides) into scal; raises *flag on bad states
-hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStream_t st);
+                         bool bound, hipStream_t st);
+// time-step bound (FP64, from the state) into the slots; raises *flag on bad states
+hipError_t launch_bound3(const Tet3Mesh &m, const void *U, hipStream_t st);
+// dt = CFL / bound (dt_fixed > 0 overrides) into scal; clears the slots
+hipError_t launch_dt3(const Tet3Mesh &m, double dt_fixed, hipStream_t st);
 // error reporting shared with the 2D ABI (dg_last_error)
 int report_error(int code, const std::string &msg);
 

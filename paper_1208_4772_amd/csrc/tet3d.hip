@@ -146,6 +146,12 @@ struct Stage3MArgs {
     const typename VT<T>::V4 *__restrict__ opsA;  // [4][NG][64]: face, then r, s, t fragments (NG = max(NGL, NGD));
                                                   // lane l of fragment z = ks MT + mt: slot z % 4 of group z / 4
     const double *__restrict__ dt;
+    // the last stage of a step: also the time-step bound of the new state
+    // (as k_cfl3) into the slots, and its state check
+    int bound;
+    double gamma;
+    unsigned long long *__restrict__ vmax;
+    int *__restrict__ flag;
 };
 
 // The stage body for FP32 (k_stage3_mfma) and FP64 (k_stage3_mfma64).  FP32
@@ -370,8 +376,10 @@ __device__ __forceinline__ void stage3_mfma_body(const Stage3MArgs<T> &a) {
                 else
                     rold = rk_read ? reinterpret_cast<const V16 *>(a.R + base)[zv] : V16{};
                 const V16 rr = a.stage == 0 ? dt * rh : a.ra * rold + dt * rh;
+                const V16 un = reinterpret_cast<const V16 *>(sU)[zv] + a.rb * rr;
                 reinterpret_cast<V16 *>(a.R + base)[zv] = rr;
-                reinterpret_cast<V16 *>(a.Uout + base)[zv] = reinterpret_cast<const V16 *>(sU)[zv] + a.rb * rr;
+                reinterpret_cast<V16 *>(a.Uout + base)[zv] = un;
+                if (a.bound) reinterpret_cast<V16 *>(sU)[zv] = un;
             }
         }
     }
@@ -382,8 +390,46 @@ __device__ __forceinline__ void stage3_mfma_body(const Stage3MArgs<T> &a) {
             a.rhs[idx] = rh;
         } else {
             const T rr = a.stage == 0 ? dt * rh : a.ra * a.R[idx] + dt * rh;
+            const T un = sU[z] + a.rb * rr;
             a.R[idx] = rr;
-            a.Uout[idx] = sU[z] + a.rb * rr;
+            a.Uout[idx] = un;
+            if (a.bound) sU[z] = un;
+        }
+    }
+    if (a.bound) {
+        // the next step's bound from the new state, node for node as k_cfl3:
+        // FP64 at every face node, maximum per block into a slot
+        __shared__ double sRed[W];
+        __syncthreads();
+        double best = 0.0;
+        int bad = 0;
+        for (int z = tid; z < ntask; z += NTH) {
+            const int e = z / NF4, q = z - e * NF4, f = q / (NF4 / 4);
+            const int v = sFM[q];
+            double u[kF3];
+#pragma unroll
+            for (int c = 0; c < kF3; ++c) u[c] = double(sU[(e * kF3 + c) * Np + v]);
+            const double ir = 1.0 / u[0];
+            const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+            const double p = (a.gamma - 1.0) * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
+            if (!(u[0] > 0.0) || !(p > 0.0) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(u[3]) ||
+                !isfinite(u[4]) || !isfinite(p))
+                bad = 1;
+            const double lam = sqrt(vx * vx + vy * vy + vz * vz) + sqrt(a.gamma * p * ir);
+            const double b = 0.5 * (P + 1.0) * (P + 1.0) * double(sG[e * kGeo3 + 21 + f]) * lam;
+            best = b > best ? b : best;
+        }
+        if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(best, off);
+            best = o > best ? o : best;
+        }
+        if (lane == 0) sRed[wave] = best;
+        __syncthreads();
+        if (tid == 0) {
+            double m = sRed[0];
+            for (int w = 1; w < W; ++w) m = sRed[w] > m ? sRed[w] : m;
+            atomicMax(a.vmax + (blockIdx.x & (kSlots3 - 1)), (unsigned long long)__double_as_longlong(m));
         }
     }
 }
@@ -596,7 +642,7 @@ void tet3_mfma_fill_opsA64(int P, const double *Dr, const double *Ds, const doub
 
 template <typename T>
 static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                              hipStream_t st) {
+                              bool bound, hipStream_t st) {
     Stage3MArgs<T> a;
     a.K = m.K;
     a.stage = stage;
@@ -614,6 +660,10 @@ static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, vo
     a.opsA = reinterpret_cast<const typename VT<T>::V4 *>(m.fp32 ? static_cast<const void *>(m.opsA)
                                                                   : static_cast<const void *>(m.opsA64));
     a.dt = m.scal + S_DT;
+    a.bound = bound ? 1 : 0;
+    a.gamma = m.gamma;
+    a.vmax = m.vmax;
+    a.flag = m.flag;
     return with_order3(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         using S = TetM<P>;
@@ -627,13 +677,13 @@ static hipError_t stage3_mfma(const Tet3Mesh &m, const void *Uin, void *Uout, vo
 }
 
 hipError_t launch_stage3(const Tet3Mesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                         hipStream_t st) {
-    return m.fp32 ? stage3_mfma<float>(m, Uin, Uout, R, rhs, stage, st)
-                  : stage3_mfma<double>(m, Uin, Uout, R, rhs, stage, st);
+                         bool bound, hipStream_t st) {
+    return m.fp32 ? stage3_mfma<float>(m, Uin, Uout, R, rhs, stage, bound && !rhs, st)
+                  : stage3_mfma<double>(m, Uin, Uout, R, rhs, stage, bound && !rhs, st);
 }
 
-hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStream_t st) {
-    hipError_t e = with_order3(m.P, [&](auto PC) {
+hipError_t launch_bound3(const Tet3Mesh &m, const void *U, hipStream_t st) {
+    return with_order3(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         const dim3 grid(tet3_blocks(m.K, P)), block(kB3);
         if (m.fp32)
@@ -644,7 +694,9 @@ hipError_t launch_cfl3(const Tet3Mesh &m, const void *U, double dt_fixed, hipStr
                                m.geo64, m.fmask, m.vmax, m.flag);
         return hipGetLastError();
     });
-    if (e != hipSuccess) return e;
+}
+
+hipError_t launch_dt3(const Tet3Mesh &m, double dt_fixed, hipStream_t st) {
     hipLaunchKernelGGL(k_dt3, dim3(1), dim3(kSlots3), 0, st, m.cfl, dt_fixed, m.vmax, m.scal);
     return hipGetLastError();
 }
