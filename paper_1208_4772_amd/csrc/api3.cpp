@@ -359,7 +359,10 @@ struct dg3_mesh {
     hipGraphExec_t graph = nullptr;
     const void *graph_U = nullptr, *graph_work = nullptr;
     double graph_dt = 0.0;
+    hipEvent_t t0 = nullptr, t1 = nullptr;   // dg3_run's timing pair, created on first use
     ~dg3_mesh() {
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
         if (graph) (void)hipGraphExecDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (done) (void)hipEventDestroy(done);
@@ -564,9 +567,9 @@ int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_ru
     const Tet3Mesh &m = h->m;
     if (nsteps >= 2)
         if (int rc = ensure_graph3(h, U, work, dt_fixed)) return rc;
-    hipEvent_t e0, e1;
-    HIP3(hipEventCreate(&e0));
-    HIP3(hipEventCreate(&e1));
+    if (!h->t0) HIP3(hipEventCreate(&h->t0));
+    if (!h->t1) HIP3(hipEventCreate(&h->t1));
+    hipEvent_t e0 = h->t0, e1 = h->t1;
     HIP3(launch_reset3(m, st));
     HIP3(hipEventRecord(e0, st));
     if (nsteps > 0) HIP3(launch_bound3(m, U, st));
@@ -583,8 +586,6 @@ int dg3_run(dg3_mesh *h, void *U, void *work, int nsteps, double dt_fixed, dg_ru
     HIP3(hipStreamSynchronize(st));
     float ms = 0.f;
     HIP3(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->steps = nsteps;
