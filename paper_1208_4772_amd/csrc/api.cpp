@@ -400,9 +400,13 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
             std::vector<double> opsA64(nA);
             mfma64_fill_opsA(P, ref.Dr.data(), ref.Ds.data(), ref.LIFT.data(), opsA64.data());
             SETUP_TRY(hipMemcpyAsync(opsA64_d, opsA64.data(), sizeof(double) * nA, hipMemcpyHostToDevice, st));
+            // slots of the time-step bound that a run's step-closing stage reduces
+            unsigned long long *vmax64_d;
+            if ((rc = m->alloc(&vmax64_d, 2 * kVmaxSlots))) return cleanup(rc);
             SETUP_TRY(hipStreamSynchronize(st));
             dm.opsA64 = opsA64_d;
             dm.geoA64 = geoA64_d;
+            dm.vmax = vmax64_d;
         }
     }
     if (dm.fp32) {
@@ -642,7 +646,28 @@ int dg_rhs(dg_mesh *m, const void *U, void *rhs, double t, void *stream) {
 // One step: dt reduction on the device, then five stages ping-ponging
 // U -> A -> B -> A -> B -> U so that no stage writes the buffer whose face
 // traces other workgroups are still reading.
+// One step of a run of an FP64 handle on the FP64 matrix cores: dt from
+// the bound the previous step's last stage (or the run's first bound) left
+// in the slots, then the five stages, the last of which reduces the next
+// bound.  The same sums as launch_cfl and the stages, so the same bits.
+static int step_fused64(dg_mesh *m, void *U, void *work, double dt, hipStream_t st) {
+    char *w = static_cast<char *>(work);
+    void *R = w + m->off_R();
+    void *A = w + m->off_A();
+    void *B = w + m->off_B();
+    void *in[5] = {U, A, B, A, B};
+    void *out[5] = {A, B, A, B, U};
+    HIP_TRY(launch_dt_slots64(m->dm, dt, st));
+    for (int s = 0; s < 5; ++s) {
+        HIP_TRY(m->time_begin(st));
+        HIP_TRY(launch_stage_mfma64(m->dm, in[s], out[s], R, nullptr, s, s == 4, st));
+        HIP_TRY(m->time_end(st));
+    }
+    return DG_OK;
+}
+
 static int step_impl(dg_mesh *m, void *U, void *work, double dt, hipStream_t st, int fused_parity = -1) {
+    if (fused_parity >= 0 && !m->dm.fp32) return step_fused64(m, U, work, dt, st);
     char *w = static_cast<char *>(work);
     void *R = w + m->off_R();
     void *A = w + m->off_A();
@@ -832,7 +857,11 @@ int dg_run(dg_mesh *m, void *U, void *work, int nsteps, dg_run_stats *stats, voi
     HIP_TRY(launch_reset_scalars(m->dm, st));
     HIP_TRY(hipMemsetAsync(m->dm.flag, 0, sizeof(int), st));
     HIP_TRY(hipEventRecord(e0, st));
-    const bool fused = m->dm.fp32 && !m->dm.weak;
+    // fused runs: the bound of each step's state comes from the previous
+    // step's last stage (FP32 matrix-core handles; FP64 handles on the FP64
+    // matrix cores, which have no viscosity)
+    const bool fused64 = !m->dm.fp32 && m->dm.opsA64 && !m->dm.av && !m->dm.weak;
+    const bool fused = (m->dm.fp32 && !m->dm.weak) || fused64;
     if (fused && nsteps > 0) {
         if (m->dm.av)
             HIP_TRY(hipMemsetAsync(m->dm.vmax, 0, 2 * kVmaxSlots * sizeof(unsigned long long), st));

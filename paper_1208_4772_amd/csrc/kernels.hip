@@ -1080,7 +1080,7 @@ hipError_t launch_stage(const DevMesh &m, const void *Uin, void *Uout, void *R, 
     // elements without viscosity, else VALU
     if (m.weak) return launch_stage_weak(m, Uin, Uout, R, rhs, stage, st);
     if (m.fp32) return launch_stage_mfma(m, Uin, Uout, R, rhs, stage, MfmaStep(), st, eps, Q);
-    if (m.opsA64 && !m.av) return launch_stage_mfma64(m, Uin, Uout, R, rhs, stage, st);
+    if (m.opsA64 && !m.av) return launch_stage_mfma64(m, Uin, Uout, R, rhs, stage, false, st);
     return stage_t<double>(m, Uin, Uout, R, rhs, stage, eps, Q, st);
 }
 

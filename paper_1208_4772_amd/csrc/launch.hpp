@@ -80,8 +80,12 @@ struct DevMesh {
 // lane order, and the launch
 size_t mfma64_opsA_values(int P);
 void mfma64_fill_opsA(int P, const double *Dr, const double *Ds, const double *LIFT, double *out);
+// bound: a run's step-closing stage, which also reduces the next step's
+// time-step bound into m.vmax (first kVmaxSlots slots) and checks the state
 hipError_t launch_stage_mfma64(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                               hipStream_t st);
+                               bool bound, hipStream_t st);
+// dt from the bound in m.vmax's slots (or the fixed step); clears them
+hipError_t launch_dt_slots64(const DevMesh &m, double dt_fixed, hipStream_t st);
 hipError_t launch_pack_affine64(const DevMesh &m, double *rec, hipStream_t st);
 
 // offsets of the operators in the ops tables

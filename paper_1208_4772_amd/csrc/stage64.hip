@@ -65,6 +65,13 @@ struct Stage64Args {
     const f64x4_t *__restrict__ opsA;  // [3][NG][64]: LIFT, -Dr, -Ds fragments; lane l of
                                        // fragment z = ks MT + mt: slot z % 4 of group z / 4
     const double *__restrict__ dt;
+    // the last stage of a step in a run: also the next step's time-step
+    // bound from the new state (as k_cfl: FP64 per face node with the
+    // per-face-node Fscale, the state check at every node) into the slots
+    int bound;
+    const double *__restrict__ fgeo;   // [K][3][3 Nfp] n_x, n_y, Fscale
+    unsigned long long *__restrict__ vmax;
+    int *__restrict__ flag;
 };
 
 // five waves per SIMD (at most 96 registers): 901 us on the 1M-element
@@ -261,8 +268,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             } else {
                 const f64x2_t rold = rk_read ? reinterpret_cast<const f64x2_t *>(a.R + base)[zv] : f64x2_t{0.0, 0.0};
                 const f64x2_t rr = a.stage == 0 ? dt * rh : a.ra * rold + dt * rh;
+                const f64x2_t un = reinterpret_cast<const f64x2_t *>(sU)[zv] + a.rb * rr;
                 reinterpret_cast<f64x2_t *>(a.R + base)[zv] = rr;
-                reinterpret_cast<f64x2_t *>(a.Uout + base)[zv] = reinterpret_cast<const f64x2_t *>(sU)[zv] + a.rb * rr;
+                reinterpret_cast<f64x2_t *>(a.Uout + base)[zv] = un;
+                if (a.bound) reinterpret_cast<f64x2_t *>(sU)[zv] = un;
             }
         }
     }
@@ -273,10 +282,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             a.rhs[idx] = rh;
         } else {
             const double rr = a.stage == 0 ? dt * rh : a.ra * a.R[idx] + dt * rh;
+            const double un = sU[z] + a.rb * rr;
             a.R[idx] = rr;
-            a.Uout[idx] = sU[z] + a.rb * rr;
+            a.Uout[idx] = un;
+            if (a.bound) sU[z] = un;
         }
     }
+    if (a.bound) {
+        __shared__ double sRed[W];
+        __syncthreads();
+        int bad = 0;
+        for (int z = tid; z < nel * Np; z += NTH) {
+            const int el = z / Np, i = z - el * Np;
+            double u[kFields];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) u[c] = sU[(el * kFields + c) * Np + i];
+            if (bad_state(a.g, u)) bad = 1;
+        }
+        double best = 0.0;
+        for (int z = tid; z < ntask; z += NTH) {
+            const int e = z / NF3, q = z - e * NF3, f = q / Nfp, j = q - f * Nfp;
+            const int v = face_node(P, f, j);
+            double u[kFields];
+#pragma unroll
+            for (int c = 0; c < kFields; ++c) u[c] = sU[(e * kFields + c) * Np + v];
+            const double b = cfl_bound(a.g, u, a.fgeo[((k0 + e) * 3 + 2) * NF3 + q], 0.0, P + 1.0);
+            best = b > best ? b : best;
+        }
+        if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(best, off);
+            best = o > best ? o : best;
+        }
+        if (lane == 0) sRed[wave] = best;
+        __syncthreads();
+        if (tid == 0) {
+            double m = sRed[0];
+            for (int w = 1; w < W; ++w) m = sRed[w] > m ? sRed[w] : m;
+            atomicMax(a.vmax + (blockIdx.x & (kVmaxSlots - 1)), (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+// dt = CFL / bound from the slots (or the fixed step), booked into the
+// scalars as k_cfl_finish does; clears the slots.  One wavefront of
+// kVmaxSlots lanes.
+__global__ void k_dt_slots64(double cfl, double dt_fixed, unsigned long long *__restrict__ slots,
+                             double *__restrict__ scal) {
+    const int l = threadIdx.x;
+    unsigned long long v = slots[l];
+    for (int off = kVmaxSlots / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    slots[l] = 0ull;
+    if (l != 0) return;
+    const double vmax = __longlong_as_double((long long)v);
+    const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * (1.0 / vmax);
+    scal[S_DT] = dt;
+    scal[S_T] += dt;
+    scal[S_DTMIN] = dt < scal[S_DTMIN] ? dt : scal[S_DTMIN];
+    scal[S_DTMAX] = dt > scal[S_DTMAX] ? dt : scal[S_DTMAX];
+    scal[S_STEPS] += 1.0;
 }
 
 // The 128-byte geometry record of each (straight) element.
@@ -341,8 +408,13 @@ hipError_t launch_pack_affine64(const DevMesh &m, double *rec, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_dt_slots64(const DevMesh &m, double dt_fixed, hipStream_t st) {
+    hipLaunchKernelGGL(k_dt_slots64, dim3(1), dim3(kVmaxSlots), 0, st, m.cfl, dt_fixed, m.vmax, m.scal);
+    return hipGetLastError();
+}
+
 hipError_t launch_stage_mfma64(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
-                               hipStream_t st) {
+                               bool bound, hipStream_t st) {
     Stage64Args a;
     a.K = m.K;
     a.stage = stage;
@@ -361,6 +433,10 @@ hipError_t launch_stage_mfma64(const DevMesh &m, const void *Uin, void *Uout, vo
     a.rec = m.geoA64;
     a.opsA = reinterpret_cast<const f64x4_t *>(m.opsA64);
     a.dt = m.scal + S_DT;
+    a.bound = bound && !rhs && m.vmax ? 1 : 0;
+    a.fgeo = m.fgeo64;
+    a.vmax = m.vmax;
+    a.flag = m.flag;
     return with_order64(m.P, [&](auto PC) {
         constexpr int P = decltype(PC)::value;
         using S = Tri64<P>;
