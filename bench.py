@@ -126,6 +126,8 @@ def stage_kernel_label(case, precision, waves, form="nodal"):
     reduces the time-step bound, k_sensor, in place of k_sensor_elem)."""
     av = "true" if case.av else "false"
     if form == "weak":
+        if precision != "fp64" and getattr(case.mesh, "node_displacement", None) is None:
+            return f"k_stage_weak_mfma<{case.P}>"   # FP32, every element straight
         return f"k_stage_weak<{'double' if precision == 'fp64' else 'float'},{case.P}>"
     if precision == "fp64":
         k = f"k_stage<double,{case.P},{av}>"

@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdg.so")
-SOURCES = ["kernels.hip", "stage_mfma.hip", "stage64.hip", "weak.hip", "tet3d.hip", "api.cpp", "api3.cpp",
+SOURCES = ["kernels.hip", "stage_mfma.hip", "stage64.hip", "weak.hip", "weak_mfma.hip", "tet3d.hip", "api.cpp", "api3.cpp",
            "refelem.cpp"]
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 

@@ -571,6 +571,17 @@ int dg_mesh_setup(const dg_mesh_desc *d, void *stream, dg_mesh **out) {
             dm.wgeoF32 = f32;
             dm.wgeoC32 = c32;
             dm.wminv32 = m32;
+            if (Kc == 0) {
+                // every element straight: the stage runs on the matrix cores
+                std::vector<float> fr(weak_mfma_opsA_values(P));
+                weak_mfma_fill_opsA(P, W.Icub.data(), W.Drc.data(), W.Dsc.data(), W.If.data(), W.Minv.data(),
+                                    fr.data());
+                float *fa;
+                if ((rc = m->alloc(&fa, fr.size()))) return cleanup(rc);
+                SETUP_TRY(hipMemcpyAsync(fa, fr.data(), sizeof(float) * fr.size(), hipMemcpyHostToDevice, st));
+                SETUP_TRY(hipStreamSynchronize(st));
+                dm.wopsA = fa;
+            }
         }
         SETUP_TRY(hipStreamSynchronize(st));
     }

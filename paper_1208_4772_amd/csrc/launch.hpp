@@ -39,6 +39,8 @@ struct DevMesh {
     const float *wops32 = nullptr, *wgeoA32 = nullptr, *wgeoF32 = nullptr, *wgeoC32 = nullptr,
                 *wminv32 = nullptr;
     const int *widx = nullptr;     // [K] curved slot of the weak-form tables or -1
+    const float *wopsA = nullptr;  // FP32 handles of straight elements: the weak form's matrix-core
+                                   // operator fragments (weak_mfma.hip)
     int wKc = 0;
     double gamma = 1.4, cfl = 0.5;
     double qinf[4] = {1, 0, 0, 2.5};
@@ -199,6 +201,12 @@ hipError_t launch_weak_geometry(const DevMesh &m, const double *x, const double 
                                 double *mass, double *work, hipStream_t st);
 hipError_t launch_stage_weak(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                              hipStream_t st);
+// the weak form on the matrix cores (weak_mfma.hip): FP32, every element straight
+size_t weak_mfma_opsA_values(int P);
+void weak_mfma_fill_opsA(int P, const double *Icub, const double *Drc, const double *Dsc, const double *If,
+                         const double *Minv, float *out);
+hipError_t launch_stage_weak_mfma(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
+                                  hipStream_t st);
 // p-refinement: U_to [K][4][np_to] = I (np_to x np_from, row-major, host) U_from
 constexpr int kProlongMax = 21 * 21;
 hipError_t launch_prolong(int K, int np_from, int np_to, const double *I, bool fp32, const void *Uf, void *Ut,

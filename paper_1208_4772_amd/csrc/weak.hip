@@ -429,6 +429,7 @@ hipError_t launch_weak_geometry(const DevMesh &m, const double *x, const double 
 
 hipError_t launch_stage_weak(const DevMesh &m, const void *Uin, void *Uout, void *R, void *rhs, int stage,
                              hipStream_t st) {
+    if (m.fp32 && m.wopsA) return launch_stage_weak_mfma(m, Uin, Uout, R, rhs, stage, st);
     return m.fp32 ? stage_weak_t<float>(m, Uin, Uout, R, rhs, stage, st)
                   : stage_weak_t<double>(m, Uin, Uout, R, rhs, stage, st);
 }

@@ -726,6 +726,12 @@ def weak_cases():
         ("supersonic_farfield_P1", lambda: meshgen.cylinder_annulus(24, 4, R2=3.0, inner_bc=meshgen.BC_FARFIELD),
          1, meshgen.freestream_state(1.5, 5.0)),
         ("vortex_config_P2", lambda: meshgen.periodic_square(16), 2, qv),
+        # straight elements only, slip walls, K = 42 (two full blocks of 16
+        # and a ragged one): FP32 runs the matrix-core kernel here
+        ("straight_channel_P1", lambda: meshgen.channel(7, 3, perm_seed=5), 1, qv),
+        ("straight_channel_P3", lambda: meshgen.channel(7, 3, perm_seed=5), 3, qv),
+        ("straight_channel_P4", lambda: meshgen.channel(7, 3, perm_seed=5), 4, qv),
+        ("straight_channel_P5", lambda: meshgen.channel(7, 3, perm_seed=5), 5, qv),
     ]
 
 
